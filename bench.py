@@ -1,0 +1,215 @@
+"""Benchmark: Primal-Dual Affine Scaling solves on one MI355X.
+
+A step is one whole LP solve (the Section 3 loop to x^T s < 1e-8: normal
+matrix, Cholesky, triangular solves, direction, ratio test and step in every
+iteration) of the m=2048, n=8192 FP64 instance from the Gaussian
+interior-feasible generator (seed 0, alpha 0.95).  Inputs and handles are
+set up in HBM before the timed region; each step solves a fresh handle from
+the same start point.
+
+Prints one JSON line: LP solves/s, plus the normal-matrix kernel's roofline
+(FP64 MFMA), the GFLOP/s of normal matrix + Cholesky, and the CPU oracle
+timed on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+  python bench.py --copy-probe      # plain 256 MiB copies (counter scaling)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "lp2048x8192": dict(m=2048, n=8192, seed=0, alpha=0.95, tol=1e-8,
+                        desc="single LP m=2048 n=8192 FP64, Gaussian A, alpha 0.95, to gap 1e-8"),
+    "lp64x256": dict(m=64, n=256, seed=0, alpha=0.95, tol=1e-8,
+                     desc="single LP m=64 n=256 FP64, Gaussian A, alpha 0.95, to gap 1e-8"),
+}
+
+
+def syrk_flops(m: int, n: int) -> float:
+    return float(m) * (m + 1) * n
+
+
+def potrf_flops(m: int) -> float:
+    return m ** 3 / 3.0 + m ** 2 / 2.0 + m / 6.0
+
+
+def source_digest() -> str:
+    p = os.path.join(ROOT, "paper_1502_03543_amd", "csrc", "kernels_syrk.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(m: int, n: int):
+    """HBM bytes per normal-matrix kernel launch from the committed counter
+    summary, or None when absent or measured on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_normal_matrix_lp2048x8192.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != source_digest() or t.get("m") != m or t.get("n") != n:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(lp, iters_gpu: int, sample_iters: int) -> dict:
+    import oracle
+
+    threads = oracle.num_threads()
+    x, y, s = lp.x0, lp.y0, lp.s0
+    t0 = time.perf_counter()
+    for _ in range(sample_iters):
+        it = oracle.iterate(lp.A, lp.b, lp.c, x, y, s, WORK["alpha"])
+        x, y, s = it.x, it.y, it.s
+    dt = (time.perf_counter() - t0) / sample_iters
+    return {
+        "value": 1.0 / (dt * max(iters_gpu, 1)),
+        "unit": "LP solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{sample_iters} oracle iterations from the start point of the same LP, "
+                   f"{dt:.2f} s each, scaled by the GPU's {iters_gpu} iterations per solve"),
+    }
+
+
+def copy_probe():
+    import torch
+
+    n = 32 * 1024 * 1024  # 256 MiB of float64
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 8 * n, "copy_probe_bytes_written": 8 * n,
+                      "launches": 5}))
+
+
+def main():
+    global WORK
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="lp2048x8192", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (the solver runs on a single "
+              "MI355X); multi-GPU runs are not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_1502_03543_amd import capi, lpgen, solver
+
+    WORK = WORKLOADS[args.workload]
+    m, n = WORK["m"], WORK["n"]
+    capi.load()
+    dev = torch.device("cuda:0")
+    lp = lpgen.gen_lp(m, n, WORK["seed"])
+    T = [torch.from_numpy(v).to(dev) for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
+    torch.cuda.synchronize()
+
+    # handles are set up before the timed region (setup time reported apart)
+    t0 = time.perf_counter()
+    handles = [solver.LP(*T, alpha=WORK["alpha"], profile=True)
+               for _ in range(args.warmup + args.steps)]
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3 / len(handles)
+
+    results = []
+    for h in handles[: args.warmup]:
+        results.append(h.solve(WORK["tol"], 500))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timed = []
+    for h in handles[args.warmup:]:
+        timed.append(h.solve(WORK["tol"], 500))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    statuses = sorted({capi.status_string(r["status"]) for r in timed})
+    iters = [r["iters"] for r in timed]
+    if statuses != ["LP_CONVERGED"] or len(set(iters)) != 1:
+        print(json.dumps({"error": "solves did not all converge identically",
+                          "statuses": statuses, "iters": iters}), file=sys.stderr)
+        sys.exit(1)
+    K = iters[0]
+
+    tims = [h.timings() for h in handles[args.warmup:]]
+    tot = {k: sum(t[k] for t in tims) for k in tims[0]}
+    launches = tot["normal_launches"]
+    kernel_ms = tot["normal_kernel_ms"] / launches
+    achieved_tflops = syrk_flops(m, n) / (kernel_ms * 1e-3) / 1e12
+    gflops_s4s5 = (tot["iterations"] * (syrk_flops(m, n) + potrf_flops(m))
+                   / ((tot["normal_ms"] + tot["potrf_ms"]) * 1e-3) / 1e9)
+    traffic = read_traffic(m, n)
+
+    out = {
+        "metric": "LP solves/s (ADA^T + Cholesky GFLOP/s reported alongside)",
+        "value": args.steps / wall,
+        "unit": "LP solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian interior-feasible LP generator)",
+        "config": {"workload": WORK["desc"], "m": m, "n": n, "seed": WORK["seed"],
+                   "alpha": WORK["alpha"], "gap_tol": WORK["tol"], "iterations_per_solve": K,
+                   "parallelism": "single GPU"},
+        "gflops_normal_plus_cholesky": gflops_s4s5,
+        "phase_ms_per_iteration": {
+            "normal_matrix_kernel": kernel_ms,
+            "normal_matrix_total": tot["normal_ms"] / tot["iterations"],
+            "cholesky": tot["potrf_ms"] / tot["iterations"],
+            "triangular_solves": tot["trsv_ms"] / tot["iterations"],
+            "gemv_direction_step": tot["other_ms"] / tot["iterations"],
+            "iteration": tot["iter_ms"] / tot["iterations"],
+        },
+        "setup_ms": setup_ms,
+        "roofline": {
+            "kernel": "k_syrk_f64<16,4> (normal matrix A D A^T, lower tiles, split-K)",
+            "bound": "mfma",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP64_MFMA_TFLOPS,
+            "traffic": traffic,
+            "algorithmic_flops_per_launch": syrk_flops(m, n),
+            "avg_launch_ms": kernel_ms,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(lp, K, args.cpu_sample_iters)
+    for h in handles:
+        h.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * pdas.h -- C ABI of the MI355X (gfx950) Primal-Dual Affine Scaling library.
+ *
+ * Problem (Section 1, equations (primal) and (dual) of Divakar, "Primal Dual
+ * Affine Scaling on GPUs", arXiv 1502.03543):
+ *     minimise c^T x  s.t.  A x = b, x >= 0        (primal)
+ *     maximise b^T y  s.t.  A^T y + s = c, s >= 0  (dual)
+ * with A in R^{m x n}, full row rank, m < n.
+ *
+ * Each iteration follows the Section 3 algorithm: solve the Newton system
+ * (bigsystem) for (dx, dy, ds), take the ratio test
+ *     psi = max{ max_j(-dx_j/x_j), max_j(-ds_j/s_j) },
+ * set alpha := 1 when psi == 1, step (x, y, s) += (alpha/psi)(dx, dy, ds),
+ * and stop as optimal after a psi == 1 step.  The Newton system is reduced as
+ * in Section 5 (equation (bigsystem2) and the formulas below it) to the normal
+ * equations (A D A^T) dy = rhs with D = diag(x/s), written with residuals:
+ *     r_d = c - A^T y - s,  rhs = b + A (d o r_d),
+ *     ds  = r_d - A^T dy,   dx  = -x - d o ds,
+ * which on a feasible iterate is the paper's (ADA^T) dy = Ax, ds = -A^T dy,
+ * dx = D(-ds) - x.  A D A^T is factored by Cholesky (Section 5.1).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major; A is m x n with leading dimension n.
+ *  - Pointers documented "device" are HIP device (or managed) memory.
+ *    Pointers documented "host" are ordinary host memory.
+ *  - The library never allocates device memory.  The caller supplies one
+ *    device workspace, sized by lp_workspace_size / lp_batch_workspace_size,
+ *    that the library carves up.  Handles themselves are small host objects.
+ *  - All device work is ordered on the stream given to lp_setup.  Functions
+ *    that return host values (info, results) synchronise that stream.
+ *  - One handle must not be used from two host threads at once.
+ *  - Nothing throws or aborts across this ABI: every function returns an
+ *    lp_status; on an error the handle keeps its last valid iterate.
+ */
+#ifndef PDAS_H
+#define PDAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same type as HIP's hipStream_t; NULL is the default stream. */
+typedef struct ihipStream_t* lp_stream_t;
+
+typedef enum lp_status {
+  LP_OK = 0,               /* call succeeded; for lp_iterate: loop continues  */
+  LP_CONVERGED = 1,        /* x^T s < gap_tol before the next direction      */
+  LP_OPTIMAL_PSI1 = 2,     /* psi == 1: full step taken, iterate optimal (Section 3) */
+  LP_OPTIMAL_ZERO_DIR = 3, /* dx = dy = ds = 0 exactly (Section 3)           */
+  LP_MAX_ITER = 4,         /* iteration limit reached                        */
+  LP_ERR_INVALID_ARG = -1, /* NULL pointer, non-finite data, alpha not in (0,1) ... */
+  LP_ERR_SHAPE = -2,       /* m < 1 or m >= n (Section 1 assumes m < n)       */
+  LP_ERR_NOT_INTERIOR = -3,/* some x0_j <= 0 or s0_j <= 0                    */
+  LP_ERR_BREAKDOWN = -4,   /* Cholesky met a pivot that is not finite and > 0 */
+  LP_ERR_NONPOS_PSI = -5,  /* psi not finite or <= 0                          */
+  LP_ERR_LOST_INTERIOR = -6,/* a step left some x_j or s_j <= 0 (step undone) */
+  LP_ERR_WORKSPACE = -7,   /* workspace NULL, too small or misaligned (256 B) */
+  LP_ERR_NO_TAPE = -8,     /* lp_backward without a recorded tape             */
+  LP_ERR_DEVICE = -9       /* a HIP runtime call failed                       */
+} lp_status;
+
+typedef enum lp_precision {
+  LP_PREC_FP64 = 0,  /* every step in FP64                                     */
+  LP_PREC_MIXED = 1  /* FP32 normal matrix and factor with FP64 refinement,
+                        switching to FP64 for good (see lp_options)            */
+} lp_precision;
+
+typedef struct lp_options {
+  double alpha;            /* step fraction, 0 < alpha < 1 (Section 3)          */
+  int32_t precision;       /* lp_precision                                       */
+  int32_t tape_capacity;   /* iterations whose start iterate is recorded for
+                              lp_backward (0: no tape)                           */
+  double mixed_switch_gap; /* MIXED: use FP64 once x^T s < this (default 1e-6)   */
+  double refine_tol;       /* MIXED: relative residual target of refinement
+                              ||rhs - M dy|| / ||rhs|| (default 1e-12)           */
+  int32_t refine_max;      /* MIXED: refinement steps before falling back to FP64
+                              (default 5)                                        */
+  int32_t profile;         /* non-zero: time each phase with HIP events on the
+                              handle's stream (see lp_get_timings)               */
+} lp_options;
+
+/* Fill *opt with the defaults: alpha 0.95, FP64, no tape, 1e-6, 1e-12, 5. */
+void lp_options_default(lp_options* opt);
+
+typedef struct lp_iter_info {
+  int32_t k;              /* index of the direction just taken (0-based)       */
+  int32_t status;         /* lp_status of the step (LP_OK while continuing)    */
+  double gap_before;      /* x^T s before the step                             */
+  double gap_after;       /* x^T s after the step                              */
+  double psi;             /* ratio-test value                                  */
+  double t;               /* step length alpha_eff / psi                       */
+  int64_t argmax;         /* j in [0,n): x-block; n + j: s-block                */
+  double min_pivot;       /* smallest Cholesky pivot (squared diagonal of L)    */
+  int32_t precision_used; /* lp_precision of this step's factor                */
+  int32_t refine_steps;   /* refinement steps taken (MIXED)                    */
+  double refine_resid;    /* final relative refinement residual (MIXED)        */
+} lp_iter_info;
+
+typedef struct lp_result {
+  int32_t status;         /* terminal lp_status                                 */
+  int32_t iters;          /* directions taken                                   */
+  double gap;             /* x^T s of the final iterate                         */
+  double primal_obj;      /* c^T x                                              */
+  double dual_obj;        /* b^T y                                              */
+} lp_result;
+
+/* Accumulated device time per phase (milliseconds, HIP events on the
+ * handle's stream) over the iterations run with lp_options.profile set. */
+typedef struct lp_timings {
+  double normal_kernel_ms; /* the normal-matrix MFMA kernel alone             */
+  double normal_ms;        /* normal matrix including the split-K reduction    */
+  double potrf_ms;         /* blocked Cholesky                                 */
+  double trsv_ms;          /* both triangular solves                           */
+  double other_ms;         /* GEMVs, direction, ratio test, step, refinement   */
+  double iter_ms;          /* whole iterations                                 */
+  int64_t iterations;      /* iterations timed                                 */
+  int64_t normal_launches; /* normal-matrix kernel launches timed              */
+} lp_timings;
+
+typedef struct lp_handle lp_handle;
+
+/* Human-readable name of a status ("LP_CONVERGED", ...). Never NULL. */
+const char* lp_status_string(int32_t status);
+
+/* Bytes of device workspace lp_setup needs for an m x n problem with the given
+ * options (opt NULL: defaults).  Errors: LP_ERR_SHAPE, LP_ERR_INVALID_ARG. */
+lp_status lp_workspace_size(int64_t m, int64_t n, const lp_options* opt, size_t* bytes);
+
+/* Create a handle for one LP.  A (device, m x n row-major) is borrowed and must
+ * stay valid and unchanged for the handle's lifetime.  b (m), c (n), x0 (n),
+ * y0 (m), s0 (n) are device vectors copied into the workspace.  workspace is a
+ * device buffer of at least lp_workspace_size bytes, 256-byte aligned, owned
+ * by the caller and used exclusively by this handle until lp_destroy.
+ * Validates: shape (LP_ERR_SHAPE), finiteness and alpha (LP_ERR_INVALID_ARG),
+ * x0 > 0 and s0 > 0 (LP_ERR_NOT_INTERIOR).  Synchronises the stream.
+ * On error *h is set to NULL. */
+lp_status lp_setup(lp_handle** h, int64_t m, int64_t n, const double* A, const double* b,
+                   const double* c, const double* x0, const double* y0, const double* s0,
+                   const lp_options* opt, void* workspace, size_t ws_bytes,
+                   lp_stream_t stream);
+
+/* One pass of the Section 3 loop body: direction, zero-direction test, ratio
+ * test, psi == 1 rule, step.  Returns LP_OK to continue, LP_OPTIMAL_PSI1,
+ * LP_OPTIMAL_ZERO_DIR or an error.  info (host, nullable) receives the
+ * step's values; the call synchronises the stream. */
+lp_status lp_iterate(lp_handle* h, lp_iter_info* info);
+
+/* The Section 3 loop: before each direction stop with LP_CONVERGED when
+ * x^T s < gap_tol, or with LP_MAX_ITER after max_iter directions from this
+ * call.  result (host, nullable) receives the summary.  log (host, nullable,
+ * max_iter entries) receives one entry per direction taken. */
+lp_status lp_solve(lp_handle* h, double gap_tol, int32_t max_iter, lp_result* result,
+                   lp_iter_info* log);
+
+/* Copy the current iterate to device buffers x (n), y (m), s (n); any may be
+ * NULL.  Stream-ordered, does not synchronise. */
+lp_status lp_get_iterate(const lp_handle* h, double* x, double* y, double* s);
+
+/* Copy the direction (dx, dy, ds) of the most recent lp_iterate to device
+ * buffers dx (n), dy (m), ds (n); any may be NULL.  Stream-ordered. */
+lp_status lp_get_direction(const lp_handle* h, double* dx, double* dy, double* ds);
+
+/* Copy the accumulated phase timings (zero when profiling is off). */
+lp_status lp_get_timings(const lp_handle* h, lp_timings* out);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+lp_status lp_destroy(lp_handle* h);
+
+/* ------------------------------------------------------------------------- */
+/* Building blocks of one iteration, exposed for callers that drive their own  */
+/* loop (and for kernel-level checks).  Same conventions as above; scratch     */
+/* comes from a caller workspace of lp_blocks_workspace_size bytes.            */
+/* ------------------------------------------------------------------------- */
+
+/* Workspace bytes for lp_normal_matrix / lp_cholesky / lp_chol_solve on an
+ * m x n problem. */
+lp_status lp_blocks_workspace_size(int64_t m, int64_t n, size_t* bytes);
+
+/* Normal matrix of the Section 5 reduced system: M = A diag(d) A^T, written to
+ * the lower triangle (i >= j) of M (device, row-major, leading dimension
+ * ldm >= m); the strict upper triangle is left untouched.  A (device, m x n
+ * row-major), d (device, n).  Stream-ordered, does not synchronise. */
+lp_status lp_normal_matrix(int64_t m, int64_t n, const double* A, const double* d, double* M,
+                           int64_t ldm, void* workspace, size_t ws_bytes, lp_stream_t stream);
+
+/* In-place Cholesky M = L L^T (Section 5.1) of the lower triangle of M
+ * (device, row-major, ldm).  Synchronises; *fail_col (host, nullable)
+ * receives -1, or the first column whose pivot is not a finite positive
+ * number (then LP_ERR_BREAKDOWN is returned and M holds partial results);
+ * *min_pivot (host, nullable) the smallest accepted pivot. */
+lp_status lp_cholesky(int64_t m, double* M, int64_t ldm, void* workspace, size_t ws_bytes,
+                      lp_stream_t stream, int64_t* fail_col, double* min_pivot);
+
+/* dy = L^-T L^-1 r for the factor left by lp_cholesky; r, dy device m-vectors
+ * (may not alias).  Stream-ordered, does not synchronise. */
+lp_status lp_chol_solve(int64_t m, const double* L, int64_t ldm, const double* r, double* dy,
+                        void* workspace, size_t ws_bytes, lp_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDAS_H */

@@ -1,0 +1,535 @@
+// C ABI of libpdas: handle, workspace carving and the Section 3 loop for one
+// LP.  The library never allocates device memory; every device buffer is a
+// slice of the caller's workspace.  All kernels run on the handle's stream.
+#include <climits>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "pdas_internal.h"
+
+using namespace pdas;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+// Carves aligned slices out of a base pointer; with base == nullptr it only
+// measures the total size.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct lp_handle {
+  long m = 0, n = 0;
+  lp_options opt{};
+  hipStream_t st = nullptr;
+  const double* A = nullptr;
+  // problem copies and the double-buffered iterate
+  double *b = nullptr, *c = nullptr;
+  double *x[2] = {}, *y[2] = {}, *s[2] = {}, *rd[2] = {};
+  int cur = 0;
+  // per-iteration vectors
+  double *d = nullptr, *w = nullptr, *rhs = nullptr, *z = nullptr, *dy = nullptr;
+  double *dx = nullptr, *ds = nullptr, *g = nullptr, *gy = nullptr;
+  // normal matrix / factor (row-major lower, ld ldm)
+  double* M = nullptr;
+  long ldm = 0;
+  int syrk_tile = 128, syrk_splits = 1;
+  double* syrk_part = nullptr;
+  size_t syrk_part_n = 0;
+  // reduction scratch
+  double *P1 = nullptr, *P2 = nullptr;
+  int nchunks = 0;
+  double* rpart = nullptr;
+  long long* ipart = nullptr;
+  int *zpart = nullptr, *npart = nullptr;
+  int ndir = 0;
+  double* gap_part = nullptr;
+  int* lost_part = nullptr;
+  int nstep = 0;
+  int* trsv_sync = nullptr;
+  int nblk = 0;
+  DevInfo* info = nullptr;
+  DevCheck* chk = nullptr;
+  double* gap_dev = nullptr;
+  // tape of start iterates for the reverse sweep
+  double* tape = nullptr;
+  int tape_cap = 0;
+  int tape_len = 0;
+  // host state
+  int k = 0;          // directions taken since setup
+  double gap = 0.0;   // x^T s of the current iterate
+  // phase timing (lp_options.profile)
+  enum { EV_ITER0, EV_SYRK0, EV_SYRKK0, EV_SYRKK1, EV_SYRK1, EV_CHOL1, EV_TRSV1, EV_ITER1, EV_N };
+  hipEvent_t ev[EV_N] = {};
+  bool profiling = false;
+  lp_timings tim{};
+};
+
+namespace {
+
+void carve(lp_handle* h, Carver& cv) {
+  const long m = h->m, n = h->n;
+  h->b = cv.take<double>(m);
+  h->c = cv.take<double>(n);
+  for (int i = 0; i < 2; ++i) {
+    h->x[i] = cv.take<double>(n);
+    h->y[i] = cv.take<double>(m);
+    h->s[i] = cv.take<double>(n);
+    h->rd[i] = cv.take<double>(n);
+  }
+  h->d = cv.take<double>(n);
+  h->w = cv.take<double>(n);
+  h->rhs = cv.take<double>(m);
+  h->z = cv.take<double>(m);
+  h->dy = cv.take<double>(m);
+  h->dx = cv.take<double>(n);
+  h->ds = cv.take<double>(n);
+  h->g = cv.take<double>(n);
+  h->gy = cv.take<double>(n);
+  h->ldm = (m + 7) / 8 * 8;
+  h->M = cv.take<double>((size_t)h->ldm * m);
+  syrk_choose((int)m, (int)n, &h->syrk_tile, &h->syrk_splits);
+  h->syrk_part_n = syrk_part_elems((int)m, h->syrk_tile, h->syrk_splits);
+  h->syrk_part = h->syrk_part_n ? cv.take<double>(h->syrk_part_n) : nullptr;
+  h->nchunks = gemv_t_chunks(m);
+  h->P1 = cv.take<double>((size_t)h->nchunks * n);
+  h->P2 = cv.take<double>((size_t)h->nchunks * n);
+  h->ndir = dir_blocks(n);
+  h->rpart = cv.take<double>(h->ndir);
+  h->ipart = cv.take<long long>(h->ndir);
+  h->zpart = cv.take<int>(h->ndir);
+  h->npart = cv.take<int>(h->ndir);
+  h->nstep = step_blocks(m, n);
+  h->gap_part = cv.take<double>(h->nstep > h->ndir ? h->nstep : h->ndir);
+  h->lost_part = cv.take<int>(h->nstep);
+  h->nblk = cdiv(m, kTB);
+  h->trsv_sync = cv.take<int>(4 + 2 * h->nblk);
+  h->info = cv.take<DevInfo>(1);
+  h->chk = cv.take<DevCheck>(1);
+  h->gap_dev = cv.take<double>(1);
+  h->tape_cap = h->opt.tape_capacity > 0 ? h->opt.tape_capacity : 0;
+  h->tape = h->tape_cap ? cv.take<double>((size_t)(h->tape_cap + 1) * (2 * n + m)) : nullptr;
+}
+
+bool valid_opts(const lp_options* o) {
+  if (!(o->alpha > 0.0 && o->alpha < 1.0)) return false;
+  if (o->precision != LP_PREC_FP64) return false;
+  if (o->tape_capacity < 0) return false;
+  return true;
+}
+
+lp_status hip_ok(hipError_t e) { return e == hipSuccess ? LP_OK : LP_ERR_DEVICE; }
+
+}  // namespace
+
+extern "C" {
+
+void lp_options_default(lp_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->alpha = 0.95;
+  o->precision = LP_PREC_FP64;
+  o->tape_capacity = 0;
+  o->mixed_switch_gap = 1e-6;
+  o->refine_tol = 1e-12;
+  o->refine_max = 5;
+}
+
+const char* lp_status_string(int32_t s) {
+  switch (s) {
+    case LP_OK: return "LP_OK";
+    case LP_CONVERGED: return "LP_CONVERGED";
+    case LP_OPTIMAL_PSI1: return "LP_OPTIMAL_PSI1";
+    case LP_OPTIMAL_ZERO_DIR: return "LP_OPTIMAL_ZERO_DIR";
+    case LP_MAX_ITER: return "LP_MAX_ITER";
+    case LP_ERR_INVALID_ARG: return "LP_ERR_INVALID_ARG";
+    case LP_ERR_SHAPE: return "LP_ERR_SHAPE";
+    case LP_ERR_NOT_INTERIOR: return "LP_ERR_NOT_INTERIOR";
+    case LP_ERR_BREAKDOWN: return "LP_ERR_BREAKDOWN";
+    case LP_ERR_NONPOS_PSI: return "LP_ERR_NONPOS_PSI";
+    case LP_ERR_LOST_INTERIOR: return "LP_ERR_LOST_INTERIOR";
+    case LP_ERR_WORKSPACE: return "LP_ERR_WORKSPACE";
+    case LP_ERR_NO_TAPE: return "LP_ERR_NO_TAPE";
+    case LP_ERR_DEVICE: return "LP_ERR_DEVICE";
+    default: return "LP_UNKNOWN_STATUS";
+  }
+}
+
+lp_status lp_workspace_size(int64_t m, int64_t n, const lp_options* opt, size_t* bytes) {
+  if (!bytes) return LP_ERR_INVALID_ARG;
+  if (m < 1 || n <= m || m > INT_MAX / 2 || n > INT_MAX / 2) return LP_ERR_SHAPE;
+  lp_options o;
+  lp_options_default(&o);
+  if (opt) o = *opt;
+  if (!valid_opts(&o)) return LP_ERR_INVALID_ARG;
+  lp_handle h;
+  h.m = m;
+  h.n = n;
+  h.opt = o;
+  Carver cv(nullptr);
+  carve(&h, cv);
+  *bytes = (cv.off + kAlign - 1) / kAlign * kAlign;
+  return LP_OK;
+}
+
+lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const double* b,
+                   const double* c, const double* x0, const double* y0, const double* s0,
+                   const lp_options* opt, void* workspace, size_t ws_bytes, lp_stream_t stream) {
+  if (!out) return LP_ERR_INVALID_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  lp_status st = lp_workspace_size(m, n, opt, &need);
+  if (st != LP_OK) return st;
+  if (!A || !b || !c || !x0 || !y0 || !s0) return LP_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < need || ((uintptr_t)workspace % kAlign) != 0)
+    return LP_ERR_WORKSPACE;
+  lp_handle* h = new (std::nothrow) lp_handle();
+  if (!h) return LP_ERR_INVALID_ARG;
+  h->m = m;
+  h->n = n;
+  lp_options_default(&h->opt);
+  if (opt) h->opt = *opt;
+  h->st = reinterpret_cast<hipStream_t>(stream);
+  h->A = A;
+  Carver cv(workspace);
+  carve(h, cv);
+  hipStream_t s = h->st;
+
+  // validation on the device: finiteness and interior start
+  hipError_t e = hipMemsetAsync(h->chk, 0, sizeof(DevCheck), s);
+  if (e == hipSuccess) {
+    launch_check_inputs(s, m, n, A, b, c, x0, y0, s0, h->chk);
+    DevCheck chk{};
+    e = hipMemcpyAsync(&chk, h->chk, sizeof(chk), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess && chk.nonfinite) st = LP_ERR_INVALID_ARG;
+    else if (e == hipSuccess && chk.nonpos) st = LP_ERR_NOT_INTERIOR;
+  }
+  if (e != hipSuccess) st = LP_ERR_DEVICE;
+  if (st != LP_OK) {
+    delete h;
+    return st;
+  }
+  // copies of the problem and the start point
+  launch_copy(s, h->b, b, m);
+  launch_copy(s, h->c, c, n);
+  launch_copy(s, h->x[0], x0, n);
+  launch_copy(s, h->y[0], y0, m);
+  launch_copy(s, h->s[0], s0, n);
+  h->cur = 0;
+  launch_fill_i32(s, h->trsv_sync, 0, 4 + 2 * h->nblk);
+  // r_d = c - A^T y0 - s0
+  launch_gemv_t(s, m, n, A, h->y[0], nullptr, h->P1, nullptr);
+  launch_dual_resid(s, m, n, h->P1, h->nchunks, h->c, h->s[0], h->rd[0]);
+  launch_gap(s, n, h->x[0], h->s[0], h->gap_part, h->gap_dev);
+  double gap = 0;
+  e = hipMemcpyAsync(&gap, h->gap_dev, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete h;
+    return LP_ERR_DEVICE;
+  }
+  h->gap = gap;
+  h->k = 0;
+  h->tape_len = 0;
+  if (h->opt.profile) {
+    h->profiling = true;
+    for (int i = 0; i < lp_handle::EV_N; ++i) {
+      if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+        lp_destroy(h);
+        return LP_ERR_DEVICE;
+      }
+    }
+  }
+  *out = h;
+  return LP_OK;
+}
+
+static void record_tape(lp_handle* h) {
+  if (!h->tape || h->tape_len > h->tape_cap) return;
+  const long m = h->m, n = h->n, row = 2 * n + m;
+  double* r = h->tape + (size_t)h->tape_len * row;
+  launch_copy(h->st, r, h->x[h->cur], n);
+  launch_copy(h->st, r + n, h->y[h->cur], m);
+  launch_copy(h->st, r + n + m, h->s[h->cur], n);
+  h->tape_len++;
+}
+
+// Enqueue one iteration (FP64) from the current iterate into the other buffer.
+static void mark(lp_handle* h, int i) {
+  if (h->profiling) (void)hipEventRecord(h->ev[i], h->st);
+}
+
+static void enqueue_iteration(lp_handle* h) {
+  const long m = h->m, n = h->n;
+  hipStream_t s = h->st;
+  const int cur = h->cur, nxt = cur ^ 1;
+  mark(h, lp_handle::EV_ITER0);
+  launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
+  launch_prep(s, n, h->x[cur], h->s[cur], h->rd[cur], h->d, h->w);
+  launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
+  mark(h, lp_handle::EV_SYRK0);
+  launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->d, h->M, h->ldm, false, h->syrk_tile,
+                  h->syrk_splits, h->syrk_part,
+                  h->profiling ? h->ev[lp_handle::EV_SYRKK0] : nullptr,
+                  h->profiling ? h->ev[lp_handle::EV_SYRKK1] : nullptr);
+  mark(h, lp_handle::EV_SYRK1);
+  launch_potrf_f64(s, (int)m, h->M, h->ldm, h->info, nullptr, 0);
+  mark(h, lp_handle::EV_CHOL1);
+  launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
+  launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
+  mark(h, lp_handle::EV_TRSV1);
+  launch_gemv_t(s, m, n, h->A, h->dy, h->y[cur], h->P1, h->P2);
+  launch_dir(s, m, n, h->P1, h->P2, h->nchunks, h->rd[cur], h->x[cur], h->s[cur], h->d, h->dx,
+             h->ds, h->gy, h->g, h->rpart, h->ipart, h->zpart, h->npart);
+  launch_step(s, m, n, h->opt.alpha, h->ndir, h->rpart, h->ipart, h->zpart, h->npart, h->dy,
+              h->x[cur], h->y[cur], h->s[cur], h->dx, h->ds, h->g, h->gy, h->c, h->x[nxt],
+              h->y[nxt], h->s[nxt], h->rd[nxt], h->gap_part, h->lost_part, h->info);
+  launch_finish(s, h->nstep, h->gap_part, h->lost_part, h->info);
+  mark(h, lp_handle::EV_ITER1);
+}
+
+static void accumulate_timings(lp_handle* h) {
+  if (!h->profiling) return;
+  float t[8] = {};
+  auto el = [&](int a, int b) {
+    float ms = 0;
+    return hipEventElapsedTime(&ms, h->ev[a], h->ev[b]) == hipSuccess ? (double)ms : 0.0;
+  };
+  typedef lp_handle H;
+  const double iter = el(H::EV_ITER0, H::EV_ITER1);
+  const double syrk = el(H::EV_SYRK0, H::EV_SYRK1);
+  const double syrkk = el(H::EV_SYRKK0, H::EV_SYRKK1);
+  const double chol = el(H::EV_SYRK1, H::EV_CHOL1);
+  const double trsv = el(H::EV_CHOL1, H::EV_TRSV1);
+  (void)t;
+  h->tim.iter_ms += iter;
+  h->tim.normal_ms += syrk;
+  h->tim.normal_kernel_ms += syrkk;
+  h->tim.potrf_ms += chol;
+  h->tim.trsv_ms += trsv;
+  h->tim.other_ms += iter - syrk - chol - trsv;
+  h->tim.iterations += 1;
+  h->tim.normal_launches += 1;
+}
+
+lp_status lp_iterate(lp_handle* h, lp_iter_info* info) {
+  if (!h) return LP_ERR_INVALID_ARG;
+  record_tape(h);
+  enqueue_iteration(h);
+  DevInfo di;
+  hipError_t e = hipMemcpyAsync(&di, h->info, sizeof(di), hipMemcpyDeviceToHost, h->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return LP_ERR_DEVICE;
+  accumulate_timings(h);
+  const lp_status st = (lp_status)di.status;
+  const bool stepped = (st == LP_OK || st == LP_OPTIMAL_PSI1);
+  if (info) {
+    info->k = h->k;
+    info->status = st;
+    info->gap_before = h->gap;
+    info->gap_after = stepped ? di.gap_after : h->gap;
+    info->psi = di.psi;
+    info->t = di.t;
+    info->argmax = di.argmax;
+    info->min_pivot = di.min_pivot;
+    info->precision_used = LP_PREC_FP64;
+    info->refine_steps = 0;
+    info->refine_resid = 0.0;
+  }
+  if (stepped) {
+    h->cur ^= 1;
+    h->gap = di.gap_after;
+    h->k++;
+  } else if (h->tape_len > 0) {
+    h->tape_len--;  // the recorded start of a step that did not happen
+  }
+  return st;
+}
+
+lp_status lp_solve(lp_handle* h, double gap_tol, int32_t max_iter, lp_result* result,
+                   lp_iter_info* log) {
+  if (!h || max_iter < 0 || !(gap_tol >= 0)) return LP_ERR_INVALID_ARG;
+  lp_status st = LP_OK;
+  int taken = 0;
+  for (;;) {
+    if (h->gap < gap_tol) {
+      st = LP_CONVERGED;
+      break;
+    }
+    if (taken >= max_iter) {
+      st = LP_MAX_ITER;
+      break;
+    }
+    lp_iter_info it;
+    st = lp_iterate(h, &it);
+    if (log && (st == LP_OK || st == LP_OPTIMAL_PSI1 || st < 0)) log[taken] = it;
+    if (st == LP_OK) {
+      ++taken;
+      continue;
+    }
+    if (st == LP_OPTIMAL_PSI1) ++taken;
+    break;
+  }
+  if (h->tape && h->tape_len <= h->tape_cap) record_tape(h);  // final iterate
+  if (result) {
+    result->status = st;
+    result->iters = taken;
+    result->gap = h->gap;
+    // objectives: c^T x and b^T y (ordered block sums)
+    double* tmp = h->gap_dev;
+    double cx = NAN, by = NAN;
+    launch_gap(h->st, h->n, h->c, h->x[h->cur], h->gap_part, tmp);
+    hipError_t e = hipMemcpyAsync(&cx, tmp, sizeof(double), hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    launch_gap(h->st, h->m, h->b, h->y[h->cur], h->gap_part, tmp);
+    if (e == hipSuccess) e = hipMemcpyAsync(&by, tmp, sizeof(double), hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) return LP_ERR_DEVICE;
+    result->primal_obj = cx;
+    result->dual_obj = by;
+  }
+  return st;
+}
+
+lp_status lp_get_iterate(const lp_handle* h, double* x, double* y, double* s) {
+  if (!h) return LP_ERR_INVALID_ARG;
+  if (x) launch_copy(h->st, x, h->x[h->cur], h->n);
+  if (y) launch_copy(h->st, y, h->y[h->cur], h->m);
+  if (s) launch_copy(h->st, s, h->s[h->cur], h->n);
+  return hip_ok(hipGetLastError());
+}
+
+lp_status lp_get_direction(const lp_handle* h, double* dx, double* dy, double* ds) {
+  if (!h) return LP_ERR_INVALID_ARG;
+  if (dx) launch_copy(h->st, dx, h->dx, h->n);
+  if (dy) launch_copy(h->st, dy, h->dy, h->m);
+  if (ds) launch_copy(h->st, ds, h->ds, h->n);
+  return hip_ok(hipGetLastError());
+}
+
+lp_status lp_get_timings(const lp_handle* h, lp_timings* out) {
+  if (!h || !out) return LP_ERR_INVALID_ARG;
+  *out = h->tim;
+  return LP_OK;
+}
+
+lp_status lp_destroy(lp_handle* h) {
+  if (!h) return LP_OK;
+  for (int i = 0; i < lp_handle::EV_N; ++i)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  delete h;
+  return LP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Building blocks
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Blocks {
+  double* part = nullptr;
+  size_t part_n = 0;
+  int tile = 128, splits = 1;
+  int* sync = nullptr;
+  DevInfo* info = nullptr;
+  double* z = nullptr;
+};
+
+void carve_blocks(long m, long n, Carver& cv, Blocks& b) {
+  syrk_choose((int)m, (int)n, &b.tile, &b.splits);
+  b.part_n = syrk_part_elems((int)m, b.tile, b.splits);
+  b.part = b.part_n ? cv.take<double>(b.part_n) : nullptr;
+  b.sync = cv.take<int>(4 + 2 * cdiv(m, kTB));
+  b.info = cv.take<DevInfo>(1);
+  b.z = cv.take<double>(m);
+}
+
+}  // namespace
+
+extern "C" {
+
+lp_status lp_blocks_workspace_size(int64_t m, int64_t n, size_t* bytes) {
+  if (!bytes) return LP_ERR_INVALID_ARG;
+  if (m < 1 || n < 1 || m > INT_MAX / 2 || n > INT_MAX / 2) return LP_ERR_SHAPE;
+  Carver cv(nullptr);
+  Blocks b;
+  carve_blocks(m, n, cv, b);
+  *bytes = (cv.off + kAlign - 1) / kAlign * kAlign;
+  return LP_OK;
+}
+
+static lp_status blocks_from(int64_t m, int64_t n, void* ws, size_t ws_bytes, Blocks& b) {
+  size_t need = 0;
+  lp_status st = lp_blocks_workspace_size(m, n, &need);
+  if (st != LP_OK) return st;
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return LP_ERR_WORKSPACE;
+  Carver cv(ws);
+  carve_blocks(m, n, cv, b);
+  return LP_OK;
+}
+
+lp_status lp_normal_matrix(int64_t m, int64_t n, const double* A, const double* d, double* M,
+                           int64_t ldm, void* workspace, size_t ws_bytes, lp_stream_t stream) {
+  if (!A || !d || !M || ldm < m) return LP_ERR_INVALID_ARG;
+  Blocks b;
+  lp_status st = blocks_from(m, n, workspace, ws_bytes, b);
+  if (st != LP_OK) return st;
+  launch_syrk_f64(reinterpret_cast<hipStream_t>(stream), (int)m, (int)n, A, n, d, M, ldm, false,
+                  b.tile, b.splits, b.part);
+  return hip_ok(hipGetLastError());
+}
+
+lp_status lp_cholesky(int64_t m, double* M, int64_t ldm, void* workspace, size_t ws_bytes,
+                      lp_stream_t stream, int64_t* fail_col, double* min_pivot) {
+  if (!M || ldm < m) return LP_ERR_INVALID_ARG;
+  Blocks b;
+  lp_status st = blocks_from(m, m + 1, workspace, ws_bytes, b);
+  if (st != LP_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  launch_iter_begin(s, b.info, b.sync, cdiv(m, kTB));
+  launch_potrf_f64(s, (int)m, M, ldm, b.info, nullptr, 0);
+  DevInfo di;
+  hipError_t e = hipMemcpyAsync(&di, b.info, sizeof(di), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return LP_ERR_DEVICE;
+  const bool broke = di.chol_fail != INT_MAX;
+  if (fail_col) *fail_col = broke ? di.chol_fail : -1;
+  if (min_pivot) *min_pivot = di.min_pivot;
+  return broke ? LP_ERR_BREAKDOWN : LP_OK;
+}
+
+lp_status lp_chol_solve(int64_t m, const double* L, int64_t ldm, const double* r, double* dy,
+                        void* workspace, size_t ws_bytes, lp_stream_t stream) {
+  if (!L || !r || !dy || r == dy || ldm < m) return LP_ERR_INVALID_ARG;
+  Blocks b;
+  lp_status st = blocks_from(m, m + 1, workspace, ws_bytes, b);
+  if (st != LP_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  launch_iter_begin(s, b.info, b.sync, cdiv(m, kTB));
+  launch_trsv_fwd(s, (int)m, L, ldm, r, b.z, b.sync, b.info);
+  launch_trsv_bwd(s, (int)m, L, ldm, b.z, dy, b.sync, b.info);
+  return hip_ok(hipGetLastError());
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal declarations shared by the HIP translation units of libpdas.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pdas.h"
+
+namespace pdas {
+
+// Per-iteration scalars written by the device and read back by the host.
+struct DevInfo {
+  double gap_before;
+  double gap_after;
+  double psi;
+  double t;
+  double min_pivot;      // bit pattern compared as int64 (positive doubles)
+  double refine_resid;
+  long long argmax;
+  int status;            // lp_status of the step
+  int chol_fail;         // first failing pivot column, or INT32_MAX
+  int zero_dir;          // 1 when dx = dy = ds = 0 exactly
+  int trsv_err;          // a bounded wait in a triangular solve gave up
+  int refine_steps;
+  int precision_used;
+  int lost;              // some updated x_j or s_j <= 0
+  int nonfinite;         // psi or a direction component is not finite
+  int pad[2];
+};
+
+// Device-side scalar results of input validation.
+struct DevCheck {
+  int nonfinite;
+  int nonpos;
+  int pad[2];
+};
+
+constexpr int kTB = 64;          // triangular-solve and Cholesky panel block
+constexpr int kGemvRows = 64;    // rows per chunk of the transposed GEMV
+constexpr int kVecThreads = 256; // threads of the elementwise kernels
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// --- vector kernels (kernels_vec.hip) -------------------------------------
+void launch_check_inputs(hipStream_t st, long m, long n, const double* A, const double* b,
+                         const double* c, const double* x, const double* y, const double* s,
+                         DevCheck* chk);
+void launch_fill_i32(hipStream_t st, int* p, int v, long count);
+void launch_iter_begin(hipStream_t st, DevInfo* info, int* trsv_sync, int nblk);
+// r_d = c - (gy + t g) - s when g != nullptr, else c - gy - s; gy = sum of chunk partials
+void launch_dual_resid(hipStream_t st, long m, long n, const double* P, int nchunks,
+                       const double* c, const double* s, double* rd);
+void launch_prep(hipStream_t st, long n, const double* x, const double* s, const double* rd,
+                 double* d, double* w);
+void launch_gemv_n(hipStream_t st, long m, long n, const double* A, const double* w,
+                   const double* b, double* out);
+void launch_gemv_t(hipStream_t st, long m, long n, const double* A, const double* v1,
+                   const double* v2, double* P1, double* P2);
+int gemv_t_chunks(long m);
+void launch_dir(hipStream_t st, long m, long n, const double* P1, const double* P2, int nchunks,
+                const double* rd, const double* x, const double* s, const double* d,
+                double* dx, double* ds, double* gy, double* g, double* rpart, long long* ipart,
+                int* zpart, int* npart);
+int dir_blocks(long n);
+void launch_step(hipStream_t st, long m, long n, double alpha, int nparts, const double* rpart,
+                 const long long* ipart, const int* zpart, const int* npart, const double* dy,
+                 const double* x, const double* y, const double* s, const double* dx,
+                 const double* ds, const double* g, const double* gy, const double* c,
+                 double* xn, double* yn, double* sn, double* rdn, double* gap_part,
+                 int* lost_part, DevInfo* info);
+int step_blocks(long m, long n);
+void launch_finish(hipStream_t st, int nparts, const double* gap_part, const int* lost_part,
+                   DevInfo* info);
+void launch_gap(hipStream_t st, long n, const double* x, const double* s, double* gap_part,
+                double* out);
+void launch_copy(hipStream_t st, double* dst, const double* src, long count);
+
+// --- normal matrix (kernels_syrk.hip) --------------------------------------
+// C (row-major lower, ldc) = X diag(w) X^T (w may be null) or, when sub,
+// C -= X X^T.  X: mm rows of length K, row stride ldx.  part: split-K scratch
+// (may be null when splits == 1).
+void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, const double* w,
+                     double* C, long ldc, bool sub, int tile, int splits, double* part,
+                     hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+size_t syrk_part_elems(int mm, int tile, int splits);
+void syrk_choose(int mm, int K, int* tile, int* splits);
+
+// --- Cholesky (kernels_chol.hip) -------------------------------------------
+// In-place lower Cholesky of M (row-major, ld), m x m; failures recorded in info.
+void launch_potrf_f64(hipStream_t st, int m, double* M, long ld, DevInfo* info, double* part,
+                      size_t part_elems);
+
+// --- triangular solves (kernels_trsv.hip) ----------------------------------
+// z = L^-1 r (fwd) then y = L^-T z (bwd); L row-major lower with ld.
+// sync: 2 + 2*nblk ints, zeroed by launch_iter_begin.
+void launch_trsv_fwd(hipStream_t st, int m, const double* L, long ld, const double* r, double* z,
+                     int* sync, DevInfo* info);
+void launch_trsv_bwd(hipStream_t st, int m, const double* L, long ld, const double* z, double* y,
+                     int* sync, DevInfo* info);
+
+}  // namespace pdas

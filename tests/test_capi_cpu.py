@@ -1,0 +1,53 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+the header declares, and its host-only entry points behave."""
+import ctypes as C
+
+from paper_1502_03543_amd import capi
+
+
+def test_exports_every_declared_symbol():
+    lib = capi.load()
+    declared = capi.declared_functions()
+    assert "lp_setup" in declared and "lp_iterate" in declared and "lp_solve" in declared
+    missing = [f for f in declared if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    for code, name in [(0, "LP_OK"), (1, "LP_CONVERGED"), (2, "LP_OPTIMAL_PSI1"),
+                       (-4, "LP_ERR_BREAKDOWN"), (-9, "LP_ERR_DEVICE"), (99, "LP_UNKNOWN_STATUS")]:
+        assert capi.status_string(code) == name
+
+
+def test_workspace_size_and_validation():
+    o = capi.lp_options()
+    capi.lp_options_default(C.byref(o))
+    assert o.alpha == 0.95 and o.precision == capi.LP_PREC_FP64
+    sz = C.c_size_t(0)
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_OK
+    small = sz.value
+    assert small > 0 and small % 256 == 0
+    assert capi.lp_workspace_size(2048, 8192, C.byref(o), C.byref(sz)) == capi.LP_OK
+    # M alone is m^2 doubles
+    assert sz.value >= 2048 * 2048 * 8
+    assert capi.lp_workspace_size(10, 10, C.byref(o), C.byref(sz)) == capi.LP_ERR_SHAPE
+    assert capi.lp_workspace_size(0, 10, C.byref(o), C.byref(sz)) == capi.LP_ERR_SHAPE
+    o.alpha = 1.0
+    assert capi.lp_workspace_size(8, 16, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+    o.alpha = 0.9
+    o.tape_capacity = 30
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_OK
+    assert sz.value >= small + 31 * (2 * 256 + 64) * 8
+
+
+def test_setup_rejects_bad_workspace_without_touching_device():
+    h = C.c_void_p()
+    o = capi.lp_options()
+    capi.lp_options_default(C.byref(o))
+    dummy = C.c_void_p(256)
+    st = capi.lp_setup(C.byref(h), 8, 16, dummy, dummy, dummy, dummy, dummy, dummy,
+                       C.byref(o), None, 0, None)
+    assert st == capi.LP_ERR_WORKSPACE and not h.value
+    st = capi.lp_setup(C.byref(h), 16, 8, dummy, dummy, dummy, dummy, dummy, dummy,
+                       C.byref(o), dummy, 1 << 30, None)
+    assert st == capi.LP_ERR_SHAPE
