@@ -74,15 +74,21 @@ typedef struct lp_options {
   int32_t tape_capacity;   /* iterations whose start iterate is recorded for
                               lp_backward (0: no tape)                           */
   double mixed_switch_gap; /* MIXED: use FP64 once x^T s < this (default 1e-6)   */
-  double refine_tol;       /* MIXED: relative residual target of refinement
-                              ||rhs - M dy|| / ||rhs|| (default 1e-12)           */
-  int32_t refine_max;      /* MIXED: refinement steps before falling back to FP64
-                              (default 5)                                        */
+  double refine_tol;       /* MIXED: refinement succeeds when the relative
+                              correction ||delta_i||/||dy|| (or, once the
+                              corrections contract by q < 1/2, the remaining
+                              error estimate ||delta_i|| q/(1-q) / ||dy||) is
+                              <= refine_tol (default 2^-46 ~ 1.4e-14)            */
+  int32_t refine_max;      /* MIXED: corrections before falling back to FP64; a
+                              correction that does not halve the previous one,
+                              or an FP32 pivot that is not positive, also falls
+                              back (default 5)                                   */
   int32_t profile;         /* non-zero: time each phase with HIP events on the
                               handle's stream (see lp_get_timings)               */
 } lp_options;
 
-/* Fill *opt with the defaults: alpha 0.95, FP64, no tape, 1e-6, 1e-12, 5. */
+/* Fill *opt with the defaults: alpha 0.95, FP64, no tape, switch gap 1e-6,
+ * refine_tol 2^-46, refine_max 5, no profiling. */
 void lp_options_default(lp_options* opt);
 
 typedef struct lp_iter_info {
@@ -96,7 +102,7 @@ typedef struct lp_iter_info {
   double min_pivot;       /* smallest Cholesky pivot (squared diagonal of L)    */
   int32_t precision_used; /* lp_precision of this step's factor                */
   int32_t refine_steps;   /* refinement steps taken (MIXED)                    */
-  double refine_resid;    /* final relative refinement residual (MIXED)        */
+  double refine_resid;    /* estimated relative error of dy after refinement   */
 } lp_iter_info;
 
 typedef struct lp_result {
@@ -166,8 +172,92 @@ lp_status lp_get_direction(const lp_handle* h, double* dx, double* dy, double* d
 /* Copy the accumulated phase timings (zero when profiling is off). */
 lp_status lp_get_timings(const lp_handle* h, lp_timings* out);
 
+/* Reverse mode through the directions taken since lp_setup, for a scalar loss
+ * on the final iterate.  Needs lp_options.tape_capacity >= that number of
+ * directions (LP_ERR_NO_TAPE otherwise).  Inputs: xbar_K (device, n; required),
+ * ybar_K (m) and sbar_K (n) (device, nullable: zero) are the loss gradients
+ * with respect to the final x, y, s.  Outputs (device, each nullable): Abar
+ * (m x n row-major), bbar (m), cbar (n), x0bar (n), y0bar (m), s0bar (n), the
+ * gradients with respect to the inputs of lp_setup.  Each recorded step is
+ * recomputed in FP64 from its start iterate and dual residual (normal matrix
+ * and Cholesky factor included; bit-identical to an FP64 forward pass), and
+ * the factor serves the solve with the symmetric M.  A psi == 1 step length
+ * is treated as constant.  Uses the handle's workspace and stream and leaves
+ * its iterate unchanged; synchronises. */
+lp_status lp_backward(lp_handle* h, const double* xbar_K, const double* ybar_K,
+                      const double* sbar_K, double* Abar, double* bbar, double* cbar,
+                      double* x0bar, double* y0bar, double* s0bar);
+
+/* Copy the start iterate of recorded step k (0 <= k < directions recorded)
+ * to device buffers x (n), y (m), s (n); any may be NULL.  LP_ERR_NO_TAPE
+ * without a tape or for k out of range.  Stream-ordered. */
+lp_status lp_tape_row(const lp_handle* h, int32_t k, double* x, double* y, double* s);
+
 /* Release the handle (host memory only; the workspace stays the caller's). */
 lp_status lp_destroy(lp_handle* h);
+
+/* ------------------------------------------------------------------------- */
+/* Batched solver: count independent LPs of individual shapes (m_i, n_i), each  */
+/* running the same Section 3 iteration.  One kernel launch advances every     */
+/* active LP by one iteration (a workgroup owns an LP for all phases, LPs taken */
+/* largest m^2 n first); iterations are replayed from a captured hipGraph.     */
+/* FP64 only.                                                                  */
+/* ------------------------------------------------------------------------- */
+typedef struct lp_batch lp_batch;
+
+/* Workspace bytes for a batch; m, n are host arrays of length count, each LP
+ * needing 1 <= m_i < n_i (LP_ERR_SHAPE otherwise). */
+lp_status lp_batch_workspace_size(int32_t count, const int64_t* m, const int64_t* n,
+                                  const lp_options* opt, size_t* bytes);
+
+/* A_packed (device) holds the matrices back to back: LP i row-major m_i x n_i
+ * starting at element a_off[i] (host array); it is borrowed for the handle's
+ * lifetime.  b and y0 (device) hold LP i's m-vector at element v_off_m[i],
+ * c, x0 and s0 (device) its n-vectors at v_off_n[i] (host arrays); they are
+ * copied.  Validation as lp_setup for every LP; any failure fails the call
+ * (first error by LP index: LP_ERR_INVALID_ARG before LP_ERR_NOT_INTERIOR).
+ * Synchronises the stream. */
+lp_status lp_batch_setup(lp_batch** h, int32_t count, const int64_t* m, const int64_t* n,
+                         const double* A_packed, const int64_t* a_off, const double* b,
+                         const double* c, const double* x0, const double* y0,
+                         const double* s0, const int64_t* v_off_m, const int64_t* v_off_n,
+                         const lp_options* opt, void* workspace, size_t ws_bytes,
+                         lp_stream_t stream);
+
+/* Run the batch until every LP has stopped: x^T s < gap_tol before a
+ * direction (LP_CONVERGED), psi == 1 (LP_OPTIMAL_PSI1), an error, or max_iter
+ * directions in total since setup (LP_MAX_ITER).  status and iters (host,
+ * count entries each, nullable) receive the per-LP outcome; *n_converged
+ * (nullable) counts LP_CONVERGED and LP_OPTIMAL_PSI1.  Returns LP_OK unless a
+ * HIP call failed. */
+lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t* status,
+                         int32_t* iters, int32_t* n_converged);
+
+/* Copy the current iterates to device buffers x (sum n_i), y (sum m_i) and
+ * s (sum n_i), packed contiguously in LP order (LP i's n-vector starts at
+ * n_0 + ... + n_{i-1}); any may be NULL.  Stream-ordered. */
+lp_status lp_batch_get_iterate(const lp_batch* h, double* x, double* y, double* s);
+
+/* Reverse mode of the batch through the directions each LP took since
+ * lp_batch_setup (needs lp_options.tape_capacity >= the largest count;
+ * LP_ERR_NO_TAPE otherwise), for a scalar loss on the final iterates.  xbar_K
+ * (required), ybar_K, sbar_K (nullable: zero) are packed like
+ * lp_batch_get_iterate's outputs; Abar (nullable) is packed like A_packed
+ * (offsets a_off); bbar, cbar, x0bar, y0bar, s0bar (nullable) are packed like
+ * the iterates.  Every recorded step is recomputed from its start iterate and
+ * dual residual in FP64 and its Cholesky factor serves the solve with M.
+ * Synchronises. */
+lp_status lp_batch_backward(lp_batch* h, const double* xbar_K, const double* ybar_K,
+                            const double* sbar_K, double* Abar, double* bbar, double* cbar,
+                            double* x0bar, double* y0bar, double* s0bar);
+
+/* Start iterates of recorded step k of every LP, packed like
+ * lp_batch_get_iterate (LPs that took fewer than k + 1 steps are left
+ * untouched).  LP_ERR_NO_TAPE without a tape or for k >= tape_capacity. */
+lp_status lp_batch_tape_row(const lp_batch* h, int32_t k, double* x, double* y, double* s);
+
+/* Release the batch handle (host memory only). */
+lp_status lp_batch_destroy(lp_batch* h);
 
 /* ------------------------------------------------------------------------- */
 /* Building blocks of one iteration, exposed for callers that drive their own  */

@@ -111,6 +111,8 @@ def _signatures(lib):
                            C.POINTER(lp_iter_info)]),
         "lp_get_iterate": (_st, [P, P, P, P]),
         "lp_get_direction": (_st, [P, P, P, P]),
+        "lp_tape_row": (_st, [P, C.c_int32, P, P, P]),
+        "lp_batch_tape_row": (_st, [P, C.c_int32, P, P, P]),
         "lp_destroy": (_st, [P]),
         "lp_get_timings": (_st, [P, C.POINTER(lp_timings)]),
         "lp_blocks_workspace_size": (_st, [_i64, _i64, C.POINTER(C.c_size_t)]),
@@ -125,6 +127,7 @@ def _signatures(lib):
                                  C.POINTER(lp_options), P, C.c_size_t, P]),
         "lp_batch_solve": (_st, [P, C.c_double, C.c_int32, P, P, C.POINTER(C.c_int32)]),
         "lp_batch_get_iterate": (_st, [P, P, P, P]),
+        "lp_batch_backward": (_st, [P, P, P, P, P, P, P, P, P, P]),
         "lp_batch_destroy": (_st, [P]),
     }
     for name, (res, args) in sig.items():
@@ -182,6 +185,8 @@ lp_iterate = _fn("lp_iterate")
 lp_solve = _fn("lp_solve")
 lp_get_iterate = _fn("lp_get_iterate")
 lp_get_direction = _fn("lp_get_direction")
+lp_tape_row = _fn("lp_tape_row")
+lp_batch_tape_row = _fn("lp_batch_tape_row")
 lp_destroy = _fn("lp_destroy")
 lp_get_timings = _fn("lp_get_timings")
 lp_blocks_workspace_size = _fn("lp_blocks_workspace_size")
@@ -193,4 +198,5 @@ lp_batch_workspace_size = _fn("lp_batch_workspace_size")
 lp_batch_setup = _fn("lp_batch_setup")
 lp_batch_solve = _fn("lp_batch_solve")
 lp_batch_get_iterate = _fn("lp_batch_get_iterate")
+lp_batch_backward = _fn("lp_batch_backward")
 lp_batch_destroy = _fn("lp_batch_destroy")

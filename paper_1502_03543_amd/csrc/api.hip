@@ -65,13 +65,35 @@ struct lp_handle {
   DevInfo* info = nullptr;
   DevCheck* chk = nullptr;
   double* gap_dev = nullptr;
-  // tape of start iterates for the reverse sweep
+  // tape of start iterates [x | y | s | r_d] for the reverse sweep
   double* tape = nullptr;
   int tape_cap = 0;
   int tape_len = 0;
+  // reverse-sweep buffers (carved when a tape is requested)
+  double *bx = nullptr, *by = nullptr, *bs = nullptr, *brd = nullptr;
+  double *xb = nullptr, *yb = nullptr, *sb = nullptr, *dsb = nullptr, *db = nullptr;
+  double *dyb = nullptr, *lam = nullptr, *rdb = nullptr, *v1 = nullptr, *v2 = nullptr;
+  double *v3 = nullptr, *bbar = nullptr, *cbar = nullptr, *tbar = nullptr, *tpart = nullptr;
   // host state
   int k = 0;          // directions taken since setup
   double gap = 0.0;   // x^T s of the current iterate
+  // mixed precision (lp_options.precision == LP_PREC_MIXED)
+  bool mixed = false;       // FP32 factor allowed at all
+  bool fp32_mode = false;   // FP32 factor still in use (switches off for good)
+  float* A32 = nullptr;     // FP32 copy of A
+  float* M32 = nullptr;     // FP32 normal matrix / factor, row-major lower
+  long ld32 = 0;
+  float* sd32 = nullptr;    // sqrt(d) in FP32
+  float* part32 = nullptr;
+  int splits32 = 1;
+  double* colsq = nullptr;  // squared column norms of A (trace of M = sum d_j c_j)
+  double* rvec = nullptr;   // refinement residual
+  double* delta = nullptr;  // refinement correction
+  double* vtmp = nullptr;   // d o A^T dy
+  double* rnorms = nullptr; // ||r||_inf, ||dy||_inf, trace(M)
+  int last_prec = LP_PREC_FP64;
+  int last_refine = 0;
+  double last_resid = 0.0;
   // phase timing (lp_options.profile)
   enum { EV_ITER0, EV_SYRK0, EV_SYRKK0, EV_SYRKK1, EV_SYRK1, EV_CHOL1, EV_TRSV1, EV_ITER1, EV_N };
   hipEvent_t ev[EV_N] = {};
@@ -121,13 +143,51 @@ void carve(lp_handle* h, Carver& cv) {
   h->info = cv.take<DevInfo>(1);
   h->chk = cv.take<DevCheck>(1);
   h->gap_dev = cv.take<double>(1);
+  if (h->opt.precision == LP_PREC_MIXED) {
+    h->ld32 = (m + 7) / 8 * 8;
+    h->A32 = cv.take<float>((size_t)m * n);
+    h->M32 = cv.take<float>((size_t)h->ld32 * m);
+    h->sd32 = cv.take<float>(n);
+    syrk_choose_f32((int)m, (int)n, &h->splits32);
+    const size_t p32 = syrk_part_elems_f32((int)m, h->splits32);
+    h->part32 = p32 ? cv.take<float>(p32) : nullptr;
+    h->colsq = cv.take<double>(n);
+    h->rvec = cv.take<double>(m);
+    h->delta = cv.take<double>(m);
+    h->vtmp = cv.take<double>(n);
+    h->rnorms = cv.take<double>(4);
+  }
   h->tape_cap = h->opt.tape_capacity > 0 ? h->opt.tape_capacity : 0;
-  h->tape = h->tape_cap ? cv.take<double>((size_t)(h->tape_cap + 1) * (2 * n + m)) : nullptr;
+  h->tape = h->tape_cap ? cv.take<double>((size_t)(h->tape_cap + 1) * (3 * n + m)) : nullptr;
+  if (h->tape_cap) {
+    h->bx = cv.take<double>(n);
+    h->by = cv.take<double>(m);
+    h->bs = cv.take<double>(n);
+    h->brd = cv.take<double>(n);
+    h->xb = cv.take<double>(n);
+    h->yb = cv.take<double>(m);
+    h->sb = cv.take<double>(n);
+    h->dsb = cv.take<double>(n);
+    h->db = cv.take<double>(n);
+    h->dyb = cv.take<double>(m);
+    h->lam = cv.take<double>(m);
+    h->rdb = cv.take<double>(n);
+    h->v1 = cv.take<double>(n);
+    h->v2 = cv.take<double>(n);
+    h->v3 = cv.take<double>(n);
+    h->bbar = cv.take<double>(m);
+    h->cbar = cv.take<double>(n);
+    h->tbar = cv.take<double>(1);
+    h->tpart = cv.take<double>(cdiv(m > n ? m : n, 256));
+  }
 }
 
 bool valid_opts(const lp_options* o) {
   if (!(o->alpha > 0.0 && o->alpha < 1.0)) return false;
-  if (o->precision != LP_PREC_FP64) return false;
+  if (o->precision != LP_PREC_FP64 && o->precision != LP_PREC_MIXED) return false;
+  if (o->precision == LP_PREC_MIXED &&
+      (!(o->refine_tol >= 0) || o->refine_max < 0 || !(o->mixed_switch_gap >= 0)))
+    return false;
   if (o->tape_capacity < 0) return false;
   return true;
 }
@@ -145,7 +205,7 @@ void lp_options_default(lp_options* o) {
   o->precision = LP_PREC_FP64;
   o->tape_capacity = 0;
   o->mixed_switch_gap = 1e-6;
-  o->refine_tol = 1e-12;
+  o->refine_tol = 0x1p-46;
   o->refine_max = 5;
 }
 
@@ -233,6 +293,12 @@ lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const
   launch_copy(s, h->s[0], s0, n);
   h->cur = 0;
   launch_fill_i32(s, h->trsv_sync, 0, 4 + 2 * h->nblk);
+  if (h->opt.precision == LP_PREC_MIXED) {
+    h->mixed = true;
+    h->fp32_mode = true;
+    launch_to_f32(s, m * n, A, h->A32);
+    launch_colsq(s, m, n, A, h->colsq);
+  }
   // r_d = c - A^T y0 - s0
   launch_gemv_t(s, m, n, A, h->y[0], nullptr, h->P1, nullptr);
   launch_dual_resid(s, m, n, h->P1, h->nchunks, h->c, h->s[0], h->rd[0]);
@@ -263,11 +329,12 @@ lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const
 
 static void record_tape(lp_handle* h) {
   if (!h->tape || h->tape_len > h->tape_cap) return;
-  const long m = h->m, n = h->n, row = 2 * n + m;
+  const long m = h->m, n = h->n, row = 3 * n + m;
   double* r = h->tape + (size_t)h->tape_len * row;
   launch_copy(h->st, r, h->x[h->cur], n);
   launch_copy(h->st, r + n, h->y[h->cur], m);
   launch_copy(h->st, r + n + m, h->s[h->cur], n);
+  launch_copy(h->st, r + 2 * n + m, h->rd[h->cur], n);
   h->tape_len++;
 }
 
@@ -276,15 +343,10 @@ static void mark(lp_handle* h, int i) {
   if (h->profiling) (void)hipEventRecord(h->ev[i], h->st);
 }
 
-static void enqueue_iteration(lp_handle* h) {
+// FP64 direction: normal matrix, Cholesky, the two triangular solves.
+static void solve_fp64(lp_handle* h) {
   const long m = h->m, n = h->n;
   hipStream_t s = h->st;
-  const int cur = h->cur, nxt = cur ^ 1;
-  mark(h, lp_handle::EV_ITER0);
-  launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
-  launch_prep(s, n, h->x[cur], h->s[cur], h->rd[cur], h->d, h->w);
-  launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
-  mark(h, lp_handle::EV_SYRK0);
   launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->d, h->M, h->ldm, false, h->syrk_tile,
                   h->syrk_splits, h->syrk_part,
                   h->profiling ? h->ev[lp_handle::EV_SYRKK0] : nullptr,
@@ -294,6 +356,111 @@ static void enqueue_iteration(lp_handle* h) {
   mark(h, lp_handle::EV_CHOL1);
   launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
   launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
+  h->last_prec = LP_PREC_FP64;
+}
+
+// Read the device info record (synchronises the stream).
+static bool read_info(lp_handle* h, DevInfo* di) {
+  hipError_t e = hipMemcpyAsync(di, h->info, sizeof(*di), hipMemcpyDeviceToHost, h->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+  return e == hipSuccess;
+}
+
+// Mixed precision direction: FP32 normal matrix (sqrt(D) column scaling) and
+// FP32 Cholesky on the matrix cores, the factor widened to FP64 for the
+// triangular solves, then FP64 iterative refinement on the matrix-free
+// residual r = rhs - A (d o (A^T dy)):  delta = L^-T L^-1 r,  dy += delta.
+// Stopping rule on the corrections: with q_i = ||delta_i|| / ||delta_{i-1}||
+// (the observed contraction), refinement has converged when
+//   ||delta_i|| / ||dy|| <= refine_tol   or   (q_i < 1/2 and
+//   ||delta_i|| q_i / (1 - q_i) / ||dy|| <= refine_tol)
+// (the second term bounds the error that remains after a geometric series
+// of further corrections).  An FP32 pivot failure, q_i >= 1/2 (stagnation),
+// or refine_max corrections without convergence fall back to the FP64 solve
+// and stay in FP64.  Returns false when a HIP call failed.
+static bool solve_mixed(lp_handle* h, bool* ok) {
+  const long m = h->m, n = h->n;
+  hipStream_t s = h->st;
+  *ok = false;
+  h->last_refine = 0;
+  h->last_resid = 0.0;
+  if (!launch_syrk_f32(s, (int)m, (int)n, h->A32, n, h->sd32, h->M32, h->ld32, false,
+                       h->splits32, h->part32,
+                       h->profiling ? h->ev[lp_handle::EV_SYRKK0] : nullptr,
+                       h->profiling ? h->ev[lp_handle::EV_SYRKK1] : nullptr))
+    return true;  // shapes the FP32 kernel does not take: FP64
+  mark(h, lp_handle::EV_SYRK1);
+  launch_potrf_f32(s, (int)m, h->M32, h->ld32, h->info);
+  mark(h, lp_handle::EV_CHOL1);
+  DevInfo di;
+  if (!read_info(h, &di)) return false;
+  if (di.chol_fail != INT_MAX) return true;
+  launch_lower_f32_to_f64(s, m, h->M32, h->ld32, h->M, h->ldm);
+  launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
+  launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
+  double prev = INFINITY;
+  for (int step = 0; step < h->opt.refine_max; ++step) {
+    launch_gemv_t(s, m, n, h->A, h->dy, nullptr, h->P1, nullptr);
+    launch_scale_partials(s, n, h->P1, h->nchunks, h->d, h->vtmp);
+    launch_gemv_n(s, m, n, h->A, h->vtmp, h->rhs, h->rvec, -1.0);
+    launch_fill_i32(s, h->trsv_sync, 0, 4 + 2 * h->nblk);
+    launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rvec, h->z, h->trsv_sync, h->info);
+    launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->delta, h->trsv_sync, h->info);
+    launch_axpy(s, m, h->delta, h->dy);
+    // ||delta||_inf, ||dy||_inf (after the update)
+    launch_refine_norms(s, m, n, h->delta, h->dy, h->d, h->colsq, h->rnorms);
+    double nr[4];
+    hipError_t e = hipMemcpyAsync(nr, h->rnorms, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return false;
+    if (!read_info(h, &di)) return false;
+    if (di.trsv_err) return true;
+    h->last_refine = step + 1;
+    const double dn = nr[0], yn = nr[1];
+    if (!std::isfinite(dn) || !std::isfinite(yn) || !(yn > 0)) break;
+    const double rel = dn / yn;
+    h->last_resid = rel;
+    if (rel <= h->opt.refine_tol) {
+      *ok = true;
+      break;
+    }
+    if (step > 0) {
+      const double q = dn / prev;
+      if (!(q < 0.5)) break;  // stagnation
+      const double rest = rel * q / (1.0 - q);
+      if (rest <= h->opt.refine_tol) {
+        h->last_resid = rest;
+        *ok = true;
+        break;
+      }
+    }
+    prev = dn;
+  }
+  if (*ok) h->last_prec = LP_PREC_MIXED;
+  return true;
+}
+
+// Enqueue one iteration from the current iterate into the other buffer.
+static bool enqueue_iteration(lp_handle* h) {
+  const long m = h->m, n = h->n;
+  hipStream_t s = h->st;
+  const int cur = h->cur, nxt = cur ^ 1;
+  if (h->fp32_mode && h->gap < h->opt.mixed_switch_gap) h->fp32_mode = false;
+  mark(h, lp_handle::EV_ITER0);
+  launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
+  launch_prep(s, n, h->x[cur], h->s[cur], h->rd[cur], h->d, h->w,
+              h->fp32_mode ? h->sd32 : nullptr);
+  launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
+  mark(h, lp_handle::EV_SYRK0);
+  bool done = false;
+  if (h->fp32_mode) {
+    if (!solve_mixed(h, &done)) return false;
+    if (!done) {
+      h->fp32_mode = false;  // stay in FP64 from now on
+      launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
+    }
+  }
+  if (!done) solve_fp64(h);
   mark(h, lp_handle::EV_TRSV1);
   launch_gemv_t(s, m, n, h->A, h->dy, h->y[cur], h->P1, h->P2);
   launch_dir(s, m, n, h->P1, h->P2, h->nchunks, h->rd[cur], h->x[cur], h->s[cur], h->d, h->dx,
@@ -303,6 +470,7 @@ static void enqueue_iteration(lp_handle* h) {
               h->y[nxt], h->s[nxt], h->rd[nxt], h->gap_part, h->lost_part, h->info);
   launch_finish(s, h->nstep, h->gap_part, h->lost_part, h->info);
   mark(h, lp_handle::EV_ITER1);
+  return true;
 }
 
 static void accumulate_timings(lp_handle* h) {
@@ -332,7 +500,7 @@ static void accumulate_timings(lp_handle* h) {
 lp_status lp_iterate(lp_handle* h, lp_iter_info* info) {
   if (!h) return LP_ERR_INVALID_ARG;
   record_tape(h);
-  enqueue_iteration(h);
+  if (!enqueue_iteration(h)) return LP_ERR_DEVICE;
   DevInfo di;
   hipError_t e = hipMemcpyAsync(&di, h->info, sizeof(di), hipMemcpyDeviceToHost, h->st);
   if (e == hipSuccess) e = hipStreamSynchronize(h->st);
@@ -350,9 +518,9 @@ lp_status lp_iterate(lp_handle* h, lp_iter_info* info) {
     info->t = di.t;
     info->argmax = di.argmax;
     info->min_pivot = di.min_pivot;
-    info->precision_used = LP_PREC_FP64;
-    info->refine_steps = 0;
-    info->refine_resid = 0.0;
+    info->precision_used = h->last_prec;
+    info->refine_steps = h->last_prec == LP_PREC_MIXED ? h->last_refine : 0;
+    info->refine_resid = h->last_prec == LP_PREC_MIXED ? h->last_resid : 0.0;
   }
   if (stepped) {
     h->cur ^= 1;
@@ -422,6 +590,85 @@ lp_status lp_get_direction(const lp_handle* h, double* dx, double* dy, double* d
   if (dx) launch_copy(h->st, dx, h->dx, h->n);
   if (dy) launch_copy(h->st, dy, h->dy, h->m);
   if (ds) launch_copy(h->st, ds, h->ds, h->n);
+  return hip_ok(hipGetLastError());
+}
+
+lp_status lp_backward(lp_handle* h, const double* xbar_K, const double* ybar_K,
+                      const double* sbar_K, double* Abar, double* bbar, double* cbar,
+                      double* x0bar, double* y0bar, double* s0bar) {
+  if (!h || !xbar_K) return LP_ERR_INVALID_ARG;
+  if (!h->tape || h->k > h->tape_cap || h->tape_len < h->k) return LP_ERR_NO_TAPE;
+  const long m = h->m, n = h->n, row = 3 * n + m;
+  const int K = h->k;
+  hipStream_t s = h->st;
+  const int nxt = h->cur ^ 1;  // scratch outputs of the recomputed steps
+  launch_copy(s, h->xb, xbar_K, n);
+  if (ybar_K) launch_copy(s, h->yb, ybar_K, m);
+  else launch_zero(s, h->yb, m);
+  if (sbar_K) launch_copy(s, h->sb, sbar_K, n);
+  else launch_zero(s, h->sb, n);
+  launch_zero(s, h->bbar, m);
+  launch_zero(s, h->cbar, n);
+  if (Abar) launch_zero(s, Abar, m * n);
+  for (int k = K - 1; k >= 0; --k) {
+    const double* r = h->tape + (size_t)k * row;
+    launch_copy(s, h->bx, r, n);
+    launch_copy(s, h->by, r + n, m);
+    launch_copy(s, h->bs, r + n + m, n);
+    launch_copy(s, h->brd, r + 2 * n + m, n);
+    // recompute step k exactly as the forward pass did (FP64)
+    launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
+    launch_prep(s, n, h->bx, h->bs, h->brd, h->d, h->w);
+    launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
+    launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->d, h->M, h->ldm, false, h->syrk_tile,
+                    h->syrk_splits, h->syrk_part);
+    launch_potrf_f64(s, (int)m, h->M, h->ldm, h->info, nullptr, 0);
+    launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
+    launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
+    launch_gemv_t(s, m, n, h->A, h->dy, h->by, h->P1, h->P2);
+    launch_dir(s, m, n, h->P1, h->P2, h->nchunks, h->brd, h->bx, h->bs, h->d, h->dx, h->ds,
+               h->gy, h->g, h->rpart, h->ipart, h->zpart, h->npart);
+    launch_step(s, m, n, h->opt.alpha, h->ndir, h->rpart, h->ipart, h->zpart, h->npart, h->dy,
+                h->bx, h->by, h->bs, h->dx, h->ds, h->g, h->gy, h->c, h->x[nxt], h->y[nxt],
+                h->s[nxt], h->rd[nxt], h->gap_part, h->lost_part, h->info);
+    // reverse of step k
+    launch_adj_tbar(s, m, n, h->xb, h->dx, h->sb, h->ds, h->yb, h->dy, h->tpart, h->tbar);
+    launch_adj_a(s, m, n, h->opt.alpha, h->info, h->tbar, h->bx, h->bs, h->d, h->dx, h->ds,
+                 h->xb, h->sb, h->yb, h->dsb, h->db, h->dyb);
+    launch_gemv_n(s, m, n, h->A, h->dsb, h->dyb, h->dyb, -1.0);
+    launch_fill_i32(s, h->trsv_sync, 0, 4 + 2 * h->nblk);
+    launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->dyb, h->z, h->trsv_sync, h->info);
+    launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->lam, h->trsv_sync, h->info);
+    launch_gemv_t(s, m, n, h->A, h->lam, nullptr, h->P1, nullptr);
+    launch_adj_b(s, m, n, h->P1, h->nchunks, h->g, h->brd, h->d, h->bx, h->bs, h->lam, h->dsb,
+                 h->db, h->xb, h->sb, h->cbar, h->rdb, h->bbar, h->v1, h->v2, h->v3);
+    launch_gemv_n(s, m, n, h->A, h->rdb, h->yb, h->yb, -1.0);
+    if (Abar) launch_rank3(s, m, n, Abar, h->dy, h->v1, h->lam, h->v2, h->by, h->v3);
+    DevInfo di;
+    hipError_t e = hipMemcpyAsync(&di, h->info, sizeof(di), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return LP_ERR_DEVICE;
+    if (di.chol_fail != INT_MAX) return LP_ERR_BREAKDOWN;
+    if (di.trsv_err) return LP_ERR_DEVICE;
+  }
+  if (x0bar) launch_copy(s, x0bar, h->xb, n);
+  if (y0bar) launch_copy(s, y0bar, h->yb, m);
+  if (s0bar) launch_copy(s, s0bar, h->sb, n);
+  if (bbar) launch_copy(s, bbar, h->bbar, m);
+  if (cbar) launch_copy(s, cbar, h->cbar, n);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  return e == hipSuccess ? LP_OK : LP_ERR_DEVICE;
+}
+
+lp_status lp_tape_row(const lp_handle* h, int32_t k, double* x, double* y, double* s) {
+  if (!h) return LP_ERR_INVALID_ARG;
+  if (!h->tape || k < 0 || k >= h->tape_len) return LP_ERR_NO_TAPE;
+  const long m = h->m, n = h->n;
+  const double* r = h->tape + (size_t)k * (3 * n + m);
+  if (x) launch_copy(h->st, x, r, n);
+  if (y) launch_copy(h->st, y, r + n, m);
+  if (s) launch_copy(h->st, s, r + n + m, n);
   return hip_ok(hipGetLastError());
 }
 

@@ -1,0 +1,453 @@
+// C ABI of the batched solver: many independent LPs, each advanced by the
+// Section 3 iteration, one kernel launch per iteration for the whole batch.
+// Iterations are captured into a hipGraph (a queue-reset node and the batch
+// kernel per iteration, several iterations per graph) and replayed until no
+// LP remains active.  The library allocates no device memory: everything is
+// carved from the caller's workspace.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "pdas_internal.h"
+
+using namespace pdas;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kItersPerGraph = 4;
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Gather the caller's vectors (arbitrary offsets) into the packed layout, and
+// check finiteness / interior start per LP.
+__global__ __launch_bounds__(256) void k_batch_gather(int count, const BatchLP* lps,
+                                                      const long long* uvm,
+                                                      const long long* uvn, const double* b,
+                                                      const double* c, const double* x0,
+                                                      const double* y0, const double* s0,
+                                                      const double* A, double* pb, double* pc,
+                                                      double* px, double* py, double* ps,
+                                                      int* flags) {
+  const int lp = blockIdx.x;
+  if (lp >= count) return;
+  const BatchLP P = lps[lp];
+  int bad = 0, nonpos = 0;
+  for (int i = threadIdx.x; i < P.m; i += 256) {
+    const double bv = b[uvm[lp] + i], yv = y0[uvm[lp] + i];
+    pb[P.vm + i] = bv;
+    py[P.vm + i] = yv;
+    bad |= !isfinite(bv) | !isfinite(yv);
+  }
+  for (int j = threadIdx.x; j < P.n; j += 256) {
+    const double cv = c[uvn[lp] + j], xv = x0[uvn[lp] + j], sv = s0[uvn[lp] + j];
+    pc[P.vn + j] = cv;
+    px[P.vn + j] = xv;
+    ps[P.vn + j] = sv;
+    bad |= !isfinite(cv) | !isfinite(xv) | !isfinite(sv);
+    nonpos |= !(xv > 0) | !(sv > 0);
+  }
+  const long mn = (long)P.m * P.n;
+  for (long e = threadIdx.x; e < mn; e += 256) bad |= !isfinite(A[P.a_off + e]);
+  if (bad) atomicOr(&flags[lp], 1);
+  if (nonpos) atomicOr(&flags[lp], 2);
+}
+
+__global__ void k_batch_init_state(int count, BatchState* st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  BatchState s{};
+  s.status = LP_OK;
+  s.iters = 0;
+  s.cur = 0;
+  s.gap = 0.0;
+  s.last_psi = 0.0;
+  s.last_t = 0.0;
+  s.last_argmax = -1;
+  st[i] = s;
+}
+
+__global__ void k_batch_copy_cur(int count, const BatchLP* lps, const BatchState* st,
+                                 double* const* xb, double* const* yb, double* const* sb,
+                                 double* x, double* y, double* s) {
+  const int lp = blockIdx.x;
+  if (lp >= count) return;
+  const BatchLP P = lps[lp];
+  const int cur = st[lp].cur;
+  for (int j = threadIdx.x; j < P.n; j += blockDim.x) {
+    if (x) x[P.vn + j] = xb[cur][P.vn + j];
+    if (s) s[P.vn + j] = sb[cur][P.vn + j];
+  }
+  for (int i = threadIdx.x; i < P.m; i += blockDim.x)
+    if (y) y[P.vm + i] = yb[cur][P.vm + i];
+}
+
+// Zero LP i's region of a matrix packed like A (offset a_off).
+__global__ void k_batch_zero_mats(int count, const BatchLP* lps, double* Ab) {
+  const int lp = blockIdx.y;
+  if (lp >= count) return;
+  const BatchLP P = lps[lp];
+  const long mn = (long)P.m * P.n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn; e += (long)gridDim.x * blockDim.x)
+    Ab[P.a_off + e] = 0.0;
+}
+
+__global__ void k_batch_tape_row(int count, const BatchLP* lps, const BatchState* st,
+                                 const double* tape, int k, double* x, double* y, double* s) {
+  const int lp = blockIdx.x;
+  if (lp >= count || k >= st[lp].iters) return;
+  const BatchLP P = lps[lp];
+  const double* r = tape + P.tape_off + (long)k * (3 * P.n + P.m);
+  for (int j = threadIdx.x; j < P.n; j += blockDim.x) {
+    if (x) x[P.vn + j] = r[j];
+    if (s) s[P.vn + j] = r[P.n + P.m + j];
+  }
+  for (int i = threadIdx.x; i < P.m; i += blockDim.x)
+    if (y) y[P.vm + i] = r[P.n + i];
+}
+
+}  // namespace
+
+struct lp_batch {
+  int count = 0;
+  lp_options opt{};
+  hipStream_t st = nullptr;
+  std::vector<BatchLP> lps_h;
+  long sum_m = 0, sum_n = 0;
+  BatchArgs args{};
+  BatchLP* lps = nullptr;
+  int* order = nullptr;
+  BatchState* state = nullptr;
+  double* bufptrs = nullptr;  // device copies of the iterate buffer pointers
+  int* flags = nullptr;
+  long long* uvm = nullptr;   // caller's vector offsets (device copies)
+  long long* uvn = nullptr;
+  BatchAdj adj{};             // reverse-sweep pools (with a tape)
+  int max_iters_run = 0;
+  int grid = 1;
+};
+
+namespace {
+
+bool batch_shapes_ok(int32_t count, const int64_t* m, const int64_t* n) {
+  if (count < 1 || !m || !n) return false;
+  for (int i = 0; i < count; ++i)
+    if (m[i] < 1 || n[i] <= m[i] || n[i] > INT_MAX / 4) return false;
+  return true;
+}
+
+void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
+  const int count = h->count;
+  h->lps_h.resize(count);
+  long vm = 0, vn = 0, moff = 0, toff = 0;
+  const int tape_cap = h->opt.tape_capacity > 0 ? h->opt.tape_capacity : 0;
+  for (int i = 0; i < count; ++i) {
+    BatchLP& P = h->lps_h[i];
+    P.m = (int)m[i];
+    P.n = (int)n[i];
+    P.ldm = (P.m + 7) / 8 * 8;
+    P.pad = 0;
+    P.a_off = 0;
+    P.vm = vm;
+    P.vn = vn;
+    P.M_off = moff;
+    P.tape_off = toff;
+    vm += P.m;
+    vn += P.n;
+    moff += (long)P.ldm * P.m;
+    toff += (long)(tape_cap + 1) * (2 * P.n + P.m);
+  }
+  h->sum_m = vm;
+  h->sum_n = vn;
+  BatchArgs& a = h->args;
+  a.count = count;
+  h->lps = cv.take<BatchLP>(count);
+  h->order = cv.take<int>(count);
+  h->state = cv.take<BatchState>(count);
+  h->flags = cv.take<int>(count);
+  h->uvm = cv.take<long long>(count);
+  h->uvn = cv.take<long long>(count);
+  a.b = cv.take<double>(vm);
+  a.c = cv.take<double>(vn);
+  for (int k = 0; k < 2; ++k) {
+    a.x[k] = cv.take<double>(vn);
+    a.y[k] = cv.take<double>(vm);
+    a.s[k] = cv.take<double>(vn);
+    a.rd[k] = cv.take<double>(vn);
+  }
+  a.d = cv.take<double>(vn);
+  a.w = cv.take<double>(vn);
+  a.g = cv.take<double>(vn);
+  a.gy = cv.take<double>(vn);
+  a.dx = cv.take<double>(vn);
+  a.ds = cv.take<double>(vn);
+  a.rhs = cv.take<double>(vm);
+  a.z = cv.take<double>(vm);
+  a.dy = cv.take<double>(vm);
+  a.M = cv.take<double>(moff);
+  a.tape_cap = tape_cap;
+  a.tape = tape_cap ? cv.take<double>(toff) : nullptr;
+  a.queue = cv.take<int>(1);
+  a.active = cv.take<int>(1);
+  h->bufptrs = cv.take<double>(6);  // x[2], y[2], s[2] pointers for get_iterate
+  if (tape_cap) {
+    BatchAdj& g = h->adj;
+    g.xb = cv.take<double>(vn);
+    g.yb = cv.take<double>(vm);
+    g.sb = cv.take<double>(vn);
+    g.dsb = cv.take<double>(vn);
+    g.db = cv.take<double>(vn);
+    g.dyb = cv.take<double>(vm);
+    g.lam = cv.take<double>(vm);
+    g.h = cv.take<double>(vn);
+    g.rdb = cv.take<double>(vn);
+    g.bbar = cv.take<double>(vm);
+    g.cbar = cv.take<double>(vn);
+    g.err = cv.take<int>(1);
+    g.Abar = nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lp_status lp_batch_workspace_size(int32_t count, const int64_t* m, const int64_t* n,
+                                  const lp_options* opt, size_t* bytes) {
+  if (!bytes) return LP_ERR_INVALID_ARG;
+  if (!batch_shapes_ok(count, m, n)) return LP_ERR_SHAPE;
+  lp_options o;
+  lp_options_default(&o);
+  if (opt) o = *opt;
+  if (!(o.alpha > 0.0 && o.alpha < 1.0) || o.tape_capacity < 0) return LP_ERR_INVALID_ARG;
+  if (o.precision != LP_PREC_FP64) return LP_ERR_INVALID_ARG;
+  lp_batch h;
+  h.count = count;
+  h.opt = o;
+  Carver cv(nullptr);
+  carve_batch(&h, m, n, cv);
+  *bytes = (cv.off + kAlign - 1) / kAlign * kAlign;
+  return LP_OK;
+}
+
+lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const int64_t* n,
+                         const double* A_packed, const int64_t* a_off, const double* b,
+                         const double* c, const double* x0, const double* y0,
+                         const double* s0, const int64_t* v_off_m, const int64_t* v_off_n,
+                         const lp_options* opt, void* workspace, size_t ws_bytes,
+                         lp_stream_t stream) {
+  if (!out) return LP_ERR_INVALID_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  lp_status st = lp_batch_workspace_size(count, m, n, opt, &need);
+  if (st != LP_OK) return st;
+  if (!A_packed || !a_off || !b || !c || !x0 || !y0 || !s0 || !v_off_m || !v_off_n)
+    return LP_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < need || ((uintptr_t)workspace % kAlign) != 0)
+    return LP_ERR_WORKSPACE;
+  lp_batch* h = new (std::nothrow) lp_batch();
+  if (!h) return LP_ERR_INVALID_ARG;
+  h->count = count;
+  lp_options_default(&h->opt);
+  if (opt) h->opt = *opt;
+  h->st = reinterpret_cast<hipStream_t>(stream);
+  Carver cv(workspace);
+  carve_batch(h, m, n, cv);
+  for (int i = 0; i < count; ++i) h->lps_h[i].a_off = a_off[i];
+  BatchArgs& a = h->args;
+  a.A = A_packed;
+  a.lps = h->lps;
+  a.order = h->order;
+  a.state = h->state;
+  a.alpha = h->opt.alpha;
+  // largest m^2 n first (longest-processing-time order)
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int p, int q) {
+    const double cp = (double)m[p] * m[p] * n[p], cq = (double)m[q] * m[q] * n[q];
+    return cp > cq;
+  });
+  hipStream_t s = h->st;
+  std::vector<long long> uvm(v_off_m, v_off_m + count), uvn(v_off_n, v_off_n + count);
+  long long* d_uvm = h->uvm;
+  long long* d_uvn = h->uvn;
+  hipError_t e =
+      hipMemcpyAsync(h->lps, h->lps_h.data(), sizeof(BatchLP) * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_uvm, uvm.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_uvn, uvn.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s);
+  double* ptrs[6] = {a.x[0], a.x[1], a.y[0], a.y[1], a.s[0], a.s[1]};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->bufptrs, ptrs, sizeof(ptrs), hipMemcpyHostToDevice, s);
+  std::vector<int> flags(count, 0);
+  if (e == hipSuccess) {
+    launch_fill_i32(s, h->flags, 0, count);
+    hipLaunchKernelGGL(k_batch_gather, dim3(count), dim3(256), 0, s, count, h->lps, d_uvm, d_uvn,
+                       b, c, x0, y0, s0, A_packed, const_cast<double*>(a.b),
+                       const_cast<double*>(a.c), a.x[0], a.y[0], a.s[0], h->flags);
+    e = hipMemcpyAsync(flags.data(), h->flags, sizeof(int) * count, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete h;
+    return LP_ERR_DEVICE;
+  }
+  for (int i = 0; i < count; ++i) {
+    if (flags[i] & 1) st = LP_ERR_INVALID_ARG;
+    else if ((flags[i] & 2) && st == LP_OK) st = LP_ERR_NOT_INTERIOR;
+  }
+  if (st != LP_OK) {
+    delete h;
+    return st;
+  }
+  hipLaunchKernelGGL(k_batch_init_state, dim3((count + 255) / 256), dim3(256), 0, s, count,
+                     h->state);
+  launch_batch_setup(s, count, h->lps, h->state, A_packed, a.c, a.x[0], a.y[0], a.s[0],
+                     a.rd[0]);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  h->grid = std::min(count, 2 * cus);
+  e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete h;
+    return LP_ERR_DEVICE;
+  }
+  *out = h;
+  return LP_OK;
+}
+
+lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t* status,
+                         int32_t* iters, int32_t* n_converged) {
+  if (!h || max_iter < 0 || !(gap_tol >= 0)) return LP_ERR_INVALID_ARG;
+  hipStream_t s = h->st;
+  BatchArgs a = h->args;
+  a.tol = gap_tol;
+  a.max_iter = max_iter;
+  // Capture kItersPerGraph iterations into one graph and replay it.  The
+  // legacy default stream cannot be captured; there the same launches are
+  // issued directly.
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipSuccess;
+  if (s != nullptr) {
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int k = 0; k < kItersPerGraph; ++k) launch_batch_iter(s, a, h->grid);
+      e = hipStreamEndCapture(s, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  }
+  int launches = 0;
+  const int max_launches = max_iter / kItersPerGraph + 2;
+  while (e == hipSuccess) {
+    if (exec) {
+      e = hipGraphLaunch(exec, s);
+    } else {
+      for (int k = 0; k < kItersPerGraph; ++k) launch_batch_iter(s, a, h->grid);
+      e = hipGetLastError();
+    }
+    int active = 0;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&active, a.active, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    ++launches;
+    if (e != hipSuccess || active == 0 || launches > max_launches) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return LP_ERR_DEVICE;
+  std::vector<BatchState> states(h->count);
+  e = hipMemcpyAsync(states.data(), h->state, sizeof(BatchState) * h->count,
+                     hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return LP_ERR_DEVICE;
+  int conv = 0;
+  h->max_iters_run = 0;
+  for (int i = 0; i < h->count; ++i) {
+    h->max_iters_run = std::max(h->max_iters_run, states[i].iters);
+    int stt = states[i].status;
+    if (stt == LP_OK) stt = LP_MAX_ITER;  // never reached with max_launches above
+    if (status) status[i] = stt;
+    if (iters) iters[i] = states[i].iters;
+    conv += (stt == LP_CONVERGED || stt == LP_OPTIMAL_PSI1);
+  }
+  if (n_converged) *n_converged = conv;
+  return LP_OK;
+}
+
+lp_status lp_batch_get_iterate(const lp_batch* h, double* x, double* y, double* s) {
+  if (!h) return LP_ERR_INVALID_ARG;
+  double* const* p = reinterpret_cast<double* const*>(h->bufptrs);
+  hipLaunchKernelGGL(k_batch_copy_cur, dim3(h->count), dim3(256), 0, h->st, h->count, h->lps,
+                     h->state, p, p + 2, p + 4, x, y, s);
+  return hipGetLastError() == hipSuccess ? LP_OK : LP_ERR_DEVICE;
+}
+
+lp_status lp_batch_backward(lp_batch* h, const double* xbar_K, const double* ybar_K,
+                            const double* sbar_K, double* Abar, double* bbar, double* cbar,
+                            double* x0bar, double* y0bar, double* s0bar) {
+  if (!h || !xbar_K) return LP_ERR_INVALID_ARG;
+  BatchArgs a = h->args;
+  if (!a.tape || h->max_iters_run > a.tape_cap) return LP_ERR_NO_TAPE;
+  hipStream_t s = h->st;
+  BatchAdj g = h->adj;
+  g.Abar = Abar;
+  launch_copy(s, g.xb, xbar_K, h->sum_n);
+  if (ybar_K) launch_copy(s, g.yb, ybar_K, h->sum_m);
+  else launch_zero(s, g.yb, h->sum_m);
+  if (sbar_K) launch_copy(s, g.sb, sbar_K, h->sum_n);
+  else launch_zero(s, g.sb, h->sum_n);
+  launch_zero(s, g.bbar, h->sum_m);
+  launch_zero(s, g.cbar, h->sum_n);
+  launch_fill_i32(s, g.err, 0, 1);
+  if (Abar) hipLaunchKernelGGL(k_batch_zero_mats, dim3(64, h->count), dim3(256), 0, s, h->count,
+                               h->lps, Abar);
+  for (int k = h->max_iters_run - 1; k >= 0; --k) launch_batch_backward(s, a, g, k, h->grid);
+  if (x0bar) launch_copy(s, x0bar, g.xb, h->sum_n);
+  if (y0bar) launch_copy(s, y0bar, g.yb, h->sum_m);
+  if (s0bar) launch_copy(s, s0bar, g.sb, h->sum_n);
+  if (bbar) launch_copy(s, bbar, g.bbar, h->sum_m);
+  if (cbar) launch_copy(s, cbar, g.cbar, h->sum_n);
+  int err = 0;
+  hipError_t e = hipMemcpyAsync(&err, g.err, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return LP_ERR_DEVICE;
+  return err ? LP_ERR_BREAKDOWN : LP_OK;
+}
+
+lp_status lp_batch_tape_row(const lp_batch* h, int32_t k, double* x, double* y, double* s) {
+  if (!h) return LP_ERR_INVALID_ARG;
+  if (!h->args.tape || k < 0 || k >= h->args.tape_cap) return LP_ERR_NO_TAPE;
+  hipLaunchKernelGGL(k_batch_tape_row, dim3(h->count), dim3(256), 0, h->st, h->count, h->lps,
+                     h->state, h->args.tape, (int)k, x, y, s);
+  return hipGetLastError() == hipSuccess ? LP_OK : LP_ERR_DEVICE;
+}
+
+lp_status lp_batch_destroy(lp_batch* h) {
+  delete h;
+  return LP_OK;
+}
+
+}  // extern "C"

@@ -14,19 +14,20 @@
 //
 // Workgroup: 256 threads = 2 x 2 wavefronts; tile BM = 8R rows by BN = 32Q
 // columns (square).  Only tiles on or below the diagonal are launched.  Both
-// operands stream through double-buffered LDS in chunks of 16 along K, laid
+// operands stream through double-buffered LDS in stages of KC along K, laid
 // out so that every LDS read of a wavefront is lane-linear (B) or a 4-way
-// broadcast (A).  The diagonal weight d is applied to the row operand while
-// it is staged.  Split-K writes per-split partial tiles that an ordered
-// second pass sums, so results do not depend on scheduling.
+// broadcast (A).  Global loads for the next stage are issued before the MFMA
+// work of the current one and consumed only when they are stored to LDS, so
+// they stay in flight during the matrix work.  The diagonal weight d is
+// applied to the row operand while it is staged.  Split-K writes per-split
+// partial tiles that an ordered second pass sums, so results do not depend
+// on scheduling.
 #include <cmath>
 
 #include "pdas_internal.h"
 
 namespace pdas {
 namespace {
-
-constexpr int KC = 16;  // K per LDS stage
 
 __device__ inline void tile_coords(int t, int& ti, int& tj) {
   int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -36,13 +37,17 @@ __device__ inline void tile_coords(int t, int& ti, int& tj) {
   tj = t - r * (r + 1) / 2;
 }
 
-// LDS index of element (row, k) of a BM x KC stage buffer.
+// LDS index of element (row, k) of a BM x KC stage buffer: blocks of 4 k by
+// 16 rows, so a wavefront's operand read is lane-linear.
 template <int BM>
 __device__ inline int lidx(int row, int k) {
   return (((k >> 2) * (BM / 16) + (row >> 4)) << 6) + ((k & 3) << 4) + (row & 15);
 }
 
-template <int R, int Q>
+// R, Q: wavefront tile (4R) x (16Q); KC: K per stage; SCALE: multiply the row
+// operand by w[k] while staging; VEC: 16-byte loads (X rows and w 16-byte
+// aligned, K even).
+template <int R, int Q, int KC, bool SCALE, bool VEC>
 __global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* __restrict__ X,
                                                   long ldx, const double* __restrict__ w,
                                                   double* __restrict__ C, long ldc, int sub,
@@ -50,7 +55,8 @@ __global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* _
                                                   double* __restrict__ part) {
   constexpr int BM = 8 * R;
   static_assert(BM == 32 * Q, "square tiles");
-  constexpr int PAIRS = BM * KC / 2 / 256;  // 16-byte pairs per thread per operand
+  constexpr int PPR = KC / 2;               // element pairs per row per stage
+  constexpr int PAIRS = BM * PPR / 256;     // pairs per thread per operand
   __shared__ double lds[2][2][BM * KC];     // [stage][operand: 0 rows, 1 cols]
 
   // XCD-aware order: consecutive tiles (sharing row panels) on one XCD.
@@ -71,7 +77,6 @@ __global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* _
   const int wr0 = (wv >> 1) * (4 * R), wc0 = (wv & 1) * (16 * Q);
   // wavefronts of a diagonal tile whose block lies strictly above the diagonal idle
   const bool active = !(ti == tj && wr0 + 4 * R <= wc0);
-  const bool vec = ((ldx & 1) == 0) && ((((uintptr_t)X) & 15) == 0);
 
   double acc[R][Q];
 #pragma unroll
@@ -79,57 +84,59 @@ __global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* _
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[r][q] = 0.0;
 
-  double pa[PAIRS][2], pb[PAIRS][2];
+  // Staging registers.  Every load address is clamped into the valid range,
+  // so the loads need no branches; elements outside the tile or the K range
+  // are zeroed when the stage is stored to LDS.  Nothing consumes the loaded
+  // values before the store, so they stay in flight during the MFMA work.
+  double2 pa[PAIRS], pb[PAIRS], pw[PAIRS];
   auto gload = [&](int st) {
     const int kb = kbeg + st * KC;
 #pragma unroll
     for (int it = 0; it < PAIRS; ++it) {
       const int p = tid + 256 * it;
-      const int row = p >> 3, k = kb + ((p & 7) << 1);
-      const int ra = row0 + row, rb = col0 + row;
-      double a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-      if (vec && k + 1 < kend) {
-        if (ra < mm) {
-          const double2 v = *reinterpret_cast<const double2*>(X + (long)ra * ldx + k);
-          a0 = v.x;
-          a1 = v.y;
-        }
-        if (rb < mm) {
-          const double2 v = *reinterpret_cast<const double2*>(X + (long)rb * ldx + k);
-          b0 = v.x;
-          b1 = v.y;
-        }
+      const int row = p / PPR, k = kb + 2 * (p % PPR);
+      const long ra = min(row0 + row, mm - 1), rb = min(col0 + row, mm - 1);
+      if (VEC) {
+        const int kc = min(k, kend - 2);
+        pa[it] = *reinterpret_cast<const double2*>(X + ra * ldx + kc);
+        pb[it] = *reinterpret_cast<const double2*>(X + rb * ldx + kc);
+        if (SCALE) pw[it] = *reinterpret_cast<const double2*>(w + kc);
       } else {
-        if (ra < mm && k < kend) a0 = X[(long)ra * ldx + k];
-        if (ra < mm && k + 1 < kend) a1 = X[(long)ra * ldx + k + 1];
-        if (rb < mm && k < kend) b0 = X[(long)rb * ldx + k];
-        if (rb < mm && k + 1 < kend) b1 = X[(long)rb * ldx + k + 1];
+        const int k0 = min(k, kend - 1), k1 = min(k + 1, kend - 1);
+        pa[it].x = X[ra * ldx + k0];
+        pa[it].y = X[ra * ldx + k1];
+        pb[it].x = X[rb * ldx + k0];
+        pb[it].y = X[rb * ldx + k1];
+        if (SCALE) {
+          pw[it].x = w[k0];
+          pw[it].y = w[k1];
+        }
       }
-      if (w) {
-        if (k < kend) a0 *= w[k];
-        if (k + 1 < kend) a1 *= w[k + 1];
-      }
-      pa[it][0] = a0;
-      pa[it][1] = a1;
-      pb[it][0] = b0;
-      pb[it][1] = b1;
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int st) {
+    const int kb = kbeg + st * KC;
 #pragma unroll
     for (int it = 0; it < PAIRS; ++it) {
       const int p = tid + 256 * it;
-      const int row = p >> 3, k = (p & 7) << 1;
-      lds[buf][0][lidx<BM>(row, k)] = pa[it][0];
-      lds[buf][0][lidx<BM>(row, k + 1)] = pa[it][1];
-      lds[buf][1][lidx<BM>(row, k)] = pb[it][0];
-      lds[buf][1][lidx<BM>(row, k + 1)] = pb[it][1];
+      const int row = p / PPR, kk = 2 * (p % PPR), k = kb + kk;
+      const bool va = row0 + row < mm, vb = col0 + row < mm;
+      const bool v0 = k < kend, v1 = k + 1 < kend;
+      double a0 = pa[it].x, a1 = pa[it].y;
+      if (SCALE) {
+        a0 *= pw[it].x;
+        a1 *= pw[it].y;
+      }
+      lds[buf][0][lidx<BM>(row, kk)] = (va && v0) ? a0 : 0.0;
+      lds[buf][0][lidx<BM>(row, kk + 1)] = (va && v1) ? a1 : 0.0;
+      lds[buf][1][lidx<BM>(row, kk)] = (vb && v0) ? pb[it].x : 0.0;
+      lds[buf][1][lidx<BM>(row, kk + 1)] = (vb && v1) ? pb[it].y : 0.0;
     }
   };
 
   if (nst > 0) {
     gload(0);
-    sstore(0);
+    sstore(0, 0);
   }
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* _
         }
       }
     }
-    if (st + 1 < nst) sstore(cur ^ 1);
+    if (st + 1 < nst) sstore(cur ^ 1, st + 1);
     __syncthreads();
   }
 
@@ -203,6 +210,165 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(int mm, double* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 normal matrix (mixed precision): M32 = (A32 diag(sd)) (A32 diag(sd))^T
+// with sd = sqrt(d) applied to both operands while staging (column scaling by
+// the square root of D keeps the FP32 operands balanced), and the same kernel
+// in subtract mode for the FP32 Cholesky trailing update.
+//
+// Instruction: v_mfma_f32_16x16x4f32.  Lane l holds
+//   A operand: rowop[i = l % 16][k = l / 16],
+//   B operand: colop[j = l % 16][k = l / 16],
+//   D result : 4 values, C[i = 4 (l / 16) + v][j = l % 16].
+// A wavefront owns a (16 R) x (16 R) output (R x R blocks); a workgroup of
+// 2 x 2 wavefronts owns a BM = 32 R square tile.  LDS layout as in the FP64
+// kernel (blocks of 4 k by 16 rows), so every operand read is lane-linear.
+template <int R, int KC, bool SCALE>
+__global__ __launch_bounds__(256) void k_syrk_f32(int mm, int K, const float* __restrict__ X,
+                                                  long ldx, const float* __restrict__ w,
+                                                  float* __restrict__ C, long ldc, int sub,
+                                                  int ntiles, int per_xcd, int kchunk,
+                                                  float* __restrict__ part) {
+  constexpr int BM = 32 * R;
+  constexpr int QPR = KC / 4;              // float4 groups per row per stage
+  constexpr int QUADS = BM * QPR / 256;    // groups per thread per operand
+  __shared__ float lds[2][2][BM * KC];
+
+  const int b = blockIdx.x;
+  const int t = (b & 7) * per_xcd + (b >> 3);
+  if (t >= ntiles) return;
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int row0 = ti * BM, col0 = tj * BM;
+  const int split = blockIdx.y;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  const int nst = (kend - kbeg + KC - 1) / KC;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr0 = (wv >> 1) * (16 * R), wc0 = (wv & 1) * (16 * R);
+  const bool active = !(ti == tj && wr0 + 16 * R <= wc0);
+
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  f4 acc[R][R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+
+  float4 pa[QUADS], pb[QUADS], pw[QUADS];
+  // Requires K % 4 == 0 and 16-byte aligned rows (checked by the launcher).
+  auto gload = [&](int st) {
+    const int kb = kbeg + st * KC;
+#pragma unroll
+    for (int it = 0; it < QUADS; ++it) {
+      const int p = tid + 256 * it;
+      const int row = p / QPR, k = kb + 4 * (p % QPR);
+      const long ra = min(row0 + row, mm - 1), rb = min(col0 + row, mm - 1);
+      const int kc = min(k, kend - 4);
+      pa[it] = *reinterpret_cast<const float4*>(X + ra * ldx + kc);
+      pb[it] = *reinterpret_cast<const float4*>(X + rb * ldx + kc);
+      if (SCALE) pw[it] = *reinterpret_cast<const float4*>(w + kc);
+    }
+  };
+  auto sstore = [&](int buf, int st) {
+    const int kb = kbeg + st * KC;
+#pragma unroll
+    for (int it = 0; it < QUADS; ++it) {
+      const int p = tid + 256 * it;
+      const int row = p / QPR, kk = 4 * (p % QPR), k = kb + kk;
+      const bool va = row0 + row < mm && k < kend, vb = col0 + row < mm && k < kend;
+      float a[4] = {pa[it].x, pa[it].y, pa[it].z, pa[it].w};
+      float bb[4] = {pb[it].x, pb[it].y, pb[it].z, pb[it].w};
+      if (SCALE) {
+        const float ww[4] = {pw[it].x, pw[it].y, pw[it].z, pw[it].w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          a[v] *= ww[v];
+          bb[v] *= ww[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        lds[buf][0][lidx<BM>(row, kk + v)] = va ? a[v] : 0.f;
+        lds[buf][1][lidx<BM>(row, kk + v)] = vb ? bb[v] : 0.f;
+      }
+    }
+  };
+
+  if (nst > 0) {
+    gload(0);
+    sstore(0, 0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) gload(st + 1);
+    if (active) {
+      const float* la = lds[cur][0];
+      const float* lb = lds[cur][1];
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        float bq[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) bq[c] = lb[lidx<BM>(wc0 + 16 * c + li, 4 * ks + lk)];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float av = la[lidx<BM>(wr0 + 16 * r + li, 4 * ks + lk)];
+#pragma unroll
+          for (int c = 0; c < R; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bq[c], acc[r][c], 0, 0, 0);
+        }
+      }
+    }
+    if (st + 1 < nst) sstore(cur ^ 1, st + 1);
+    __syncthreads();
+  }
+
+  if (!active) return;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = wr0 + 16 * r + 4 * lk + v, lc = wc0 + 16 * c + li;
+        if (part) {
+          part[((long)split * ntiles + t) * (BM * BM) + lr * BM + lc] = acc[r][c][v];
+        } else {
+          const int gr = row0 + lr, gc = col0 + lc;
+          if (gr < mm && gc <= gr) {
+            float* cp = C + (long)gr * ldc + gc;
+            *cp = sub ? (*cp - acc[r][c][v]) : acc[r][c][v];
+          }
+        }
+      }
+}
+
+template <int BM>
+__global__ __launch_bounds__(256) void k_syrk_reduce_f32(int mm, float* __restrict__ C, long ldc,
+                                                         int sub, int ntiles, int splits,
+                                                         const float* __restrict__ part) {
+  const int t = blockIdx.x;
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int row0 = ti * BM, col0 = tj * BM;
+  for (int e = threadIdx.x; e < BM * BM; e += 256) {
+    const int lr = e / BM, lc = e % BM;
+    const int gr = row0 + lr, gc = col0 + lc;
+    if (gr >= mm || gc > gr) continue;
+    float v = 0.f;
+    for (int s = 0; s < splits; ++s) v += part[((long)s * ntiles + t) * (BM * BM) + e];
+    float* cp = C + (long)gr * ldc + gc;
+    *cp = sub ? (*cp - v) : v;
+  }
+}
+
+constexpr int kKC128 = 32;  // K per stage of the 128 x 128 tile kernel
+constexpr int kKC64 = 32;   // and of the 64 x 64 one
+
 }  // namespace
 
 size_t syrk_part_elems(int mm, int tile, int splits) {
@@ -231,20 +397,38 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
   const int nt = cdiv(mm, tile);
   const int ntiles = nt * (nt + 1) / 2;
   const int per_xcd = cdiv(ntiles, 8);
-  int kchunk = cdiv(cdiv(K, splits), KC) * KC;
+  const int kc = tile == 128 ? kKC128 : kKC64;
+  int kchunk = cdiv(cdiv(K, splits), kc) * kc;
   if (splits <= 1 || !part) {
     splits = 1;
     kchunk = K;
     part = nullptr;
   }
   dim3 grid(8 * per_xcd, splits);
+  const bool vec = ((ldx & 1) == 0) && (((uintptr_t)X & 15) == 0) && ((K & 1) == 0) &&
+                   (!w || (((uintptr_t)w & 15) == 0));
   if (ev_begin) (void)hipEventRecord(ev_begin, st);
-  if (tile == 128)
-    hipLaunchKernelGGL((k_syrk_f64<16, 4>), grid, dim3(256), 0, st, mm, K, X, ldx, w, C, ldc,
-                       (int)sub, ntiles, per_xcd, kchunk, part);
-  else
-    hipLaunchKernelGGL((k_syrk_f64<8, 2>), grid, dim3(256), 0, st, mm, K, X, ldx, w, C, ldc,
-                       (int)sub, ntiles, per_xcd, kchunk, part);
+#define PDAS_SYRK(R_, Q_, KC_, S_, V_)                                                        \
+  hipLaunchKernelGGL((k_syrk_f64<R_, Q_, KC_, S_, V_>), grid, dim3(256), 0, st, mm, K, X, ldx, \
+                     w, C, ldc, (int)sub, ntiles, per_xcd, kchunk, part)
+  if (tile == 128) {
+    if (w) {
+      if (vec) PDAS_SYRK(16, 4, kKC128, true, true);
+      else PDAS_SYRK(16, 4, kKC128, true, false);
+    } else {
+      if (vec) PDAS_SYRK(16, 4, kKC128, false, true);
+      else PDAS_SYRK(16, 4, kKC128, false, false);
+    }
+  } else {
+    if (w) {
+      if (vec) PDAS_SYRK(8, 2, kKC64, true, true);
+      else PDAS_SYRK(8, 2, kKC64, true, false);
+    } else {
+      if (vec) PDAS_SYRK(8, 2, kKC64, false, true);
+      else PDAS_SYRK(8, 2, kKC64, false, false);
+    }
+  }
+#undef PDAS_SYRK
   if (ev_end) (void)hipEventRecord(ev_end, st);
   if (part) {
     if (tile == 128)
@@ -254,6 +438,51 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
       hipLaunchKernelGGL(k_syrk_reduce<64>, dim3(ntiles), dim3(256), 0, st, mm, C, ldc,
                          (int)sub, ntiles, splits, part);
   }
+}
+
+size_t syrk_part_elems_f32(int mm, int splits) {
+  if (splits <= 1) return 0;
+  const long nt = cdiv(mm, 128);
+  return (size_t)splits * (size_t)(nt * (nt + 1) / 2) * 128u * 128u;
+}
+
+void syrk_choose_f32(int mm, int K, int* splits) {
+  const long nt = cdiv(mm, 128);
+  const long ntiles = nt * (nt + 1) / 2;
+  int s = 1;
+  while (ntiles * s < 512 && (long)K / (2 * s) >= 512) s *= 2;
+  *splits = s;
+}
+
+bool launch_syrk_f32(hipStream_t st, int mm, int K, const float* X, long ldx, const float* w,
+                     float* C, long ldc, bool sub, int splits, float* part, hipEvent_t ev_begin,
+                     hipEvent_t ev_end) {
+  if (mm <= 0) return true;
+  // 16-byte loads need 4-aligned K and rows
+  if ((K & 3) || (ldx & 3) || ((uintptr_t)X & 15) || (w && ((uintptr_t)w & 15))) return false;
+  constexpr int BM = 128, KC = 32;
+  const int nt = cdiv(mm, BM);
+  const int ntiles = nt * (nt + 1) / 2;
+  const int per_xcd = cdiv(ntiles, 8);
+  int kchunk = cdiv(cdiv(K, splits), KC) * KC;
+  if (splits <= 1 || !part) {
+    splits = 1;
+    kchunk = K;
+    part = nullptr;
+  }
+  dim3 grid(8 * per_xcd, splits);
+  if (ev_begin) (void)hipEventRecord(ev_begin, st);
+  if (w)
+    hipLaunchKernelGGL((k_syrk_f32<4, KC, true>), grid, dim3(256), 0, st, mm, K, X, ldx, w, C,
+                       ldc, (int)sub, ntiles, per_xcd, kchunk, part);
+  else
+    hipLaunchKernelGGL((k_syrk_f32<4, KC, false>), grid, dim3(256), 0, st, mm, K, X, ldx, w, C,
+                       ldc, (int)sub, ntiles, per_xcd, kchunk, part);
+  if (ev_end) (void)hipEventRecord(ev_end, st);
+  if (part)
+    hipLaunchKernelGGL(k_syrk_reduce_f32<BM>, dim3(ntiles), dim3(256), 0, st, mm, C, ldc,
+                       (int)sub, ntiles, splits, part);
+  return true;
 }
 
 }  // namespace pdas

@@ -6,8 +6,13 @@
 // on the ready flags of blocks with smaller tickets, which have all started,
 // so the wait graph is acyclic.  Every wait is bounded: after ~2^22 polls the
 // solve records an error in the iteration info and every block finishes.
-// Off-diagonal blocks are applied as soon as their flags are set (coalesced,
-// lane = column); the 64 x 64 diagonal block is solved by one wavefront.
+//
+// Off-diagonal blocks are applied as their flags are set; each block's
+// coefficients are loaded before its flag is awaited, so only the short
+// product with the newly published values sits on the critical path.  The
+// 64 x 64 diagonal block is solved by one wavefront with its row (column) of
+// L in registers and the solved entries broadcast with readlane (uniform
+// operands, no memory traffic inside the recurrence).
 #include <cmath>
 
 #include "pdas_internal.h"
@@ -22,6 +27,12 @@ __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
 }
 
 // Thread 0 waits until flag != 0; returns false when the solve is aborted.
@@ -45,6 +56,11 @@ __device__ bool wait_flag(int* flag, DevInfo* info, int* s_abort) {
   return true;
 }
 
+__device__ inline void publish(int* flag) {
+  __threadfence();
+  __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(256) void k_trsv_fwd(int m, const double* __restrict__ L, long ld,
                                                   const double* __restrict__ r, double* z,
                                                   int* sync, DevInfo* info) {
@@ -62,7 +78,6 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(int m, const double* __restric
   const int i0 = rb * TB;
   const int rows = min(TB, m - i0);
 
-  // diagonal block (lower), identity padding
   for (int e = tid; e < TB * TB; e += 256) {
     const int ii = e / TB, k = e % TB;
     double v = 0.0;
@@ -75,17 +90,18 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(int m, const double* __restric
   double acc[TB / 4];
 #pragma unroll
   for (int k = 0; k < TB / 4; ++k) acc[k] = 0.0;
-  bool ok = true;
-  for (int qb = 0; qb < rb && ok; ++qb) {
-    ok = wait_flag(&flags[qb], info, &s_abort);
-    if (!ok) break;
+  for (int qb = 0; qb < rb; ++qb) {
     const int col = qb * TB + lane;
-    const double zc = z[col];
+    double lv[TB / 4];
 #pragma unroll
     for (int k = 0; k < TB / 4; ++k) {
       const int ii = wv + 4 * k;
-      if (ii < rows) acc[k] += L[(long)(i0 + ii) * ld + col] * zc;
+      lv[k] = (ii < rows) ? L[(long)(i0 + ii) * ld + col] : 0.0;
     }
+    if (!wait_flag(&flags[qb], info, &s_abort)) break;
+    const double zc = z[col];
+#pragma unroll
+    for (int k = 0; k < TB / 4; ++k) acc[k] += lv[k] * zc;
   }
 #pragma unroll
   for (int k = 0; k < TB / 4; ++k) {
@@ -95,16 +111,20 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(int m, const double* __restric
   __syncthreads();
 
   if (wv == 0) {
+    double Lr[TB];
+#pragma unroll
+    for (int j = 0; j < TB; ++j) Lr[j] = Ld[lane][j];
+    const double dl = 1.0 / Ld[lane][lane];
     double val = (lane < rows) ? (r[i0 + lane] - sacc[lane]) : 0.0;
     double mine = 0.0;
+#pragma unroll
     for (int j = 0; j < TB; ++j) {
-      const double zj = __shfl(val, j, 64) / Ld[j][j];
+      const double zj = readlane_d(val, j) * readlane_d(dl, j);
       if (lane == j) mine = zj;
-      if (lane > j) val -= Ld[lane][j] * zj;
+      if (lane > j) val -= Lr[j] * zj;
     }
     if (lane < rows) z[i0 + lane] = mine;
-    __threadfence();
-    if (lane == 0) __hip_atomic_store(&flags[rb], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) publish(&flags[rb]);
   }
 }
 
@@ -136,36 +156,41 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(int m, const double* __restric
 
   // acc_c = sum over later blocks qb of sum_i L[i][c0 + c] y[i]; lane = column c
   double acc = 0.0;
-  bool ok = true;
-  for (int qb = nblk - 1; qb > rb && ok; --qb) {
-    ok = wait_flag(&flags[qb], info, &s_abort);
-    if (!ok) break;
+  for (int qb = nblk - 1; qb > rb; --qb) {
     const int rows = min(TB, m - qb * TB);
-    if (lane < cols) {
-      for (int k = 0; k < TB / 4; ++k) {
-        const int ii = wv + 4 * k;
-        if (ii < rows) {
-          const int i = qb * TB + ii;
-          acc += L[(long)i * ld + c0 + lane] * y[i];
-        }
-      }
+    double lv[TB / 4];
+#pragma unroll
+    for (int k = 0; k < TB / 4; ++k) {
+      const int ii = wv + 4 * k;
+      lv[k] = (lane < cols && ii < rows) ? L[(long)(qb * TB + ii) * ld + c0 + lane] : 0.0;
+    }
+    if (!wait_flag(&flags[qb], info, &s_abort)) break;
+#pragma unroll
+    for (int k = 0; k < TB / 4; ++k) {
+      const int ii = wv + 4 * k;
+      if (ii < rows) acc += lv[k] * y[qb * TB + ii];
     }
   }
   sacc[wv][lane] = acc;
   __syncthreads();
 
   if (wv == 0) {
+    // column `lane` of the diagonal block: Lc[j] = L[c0 + j][c0 + lane]
+    double Lc[TB];
+#pragma unroll
+    for (int j = 0; j < TB; ++j) Lc[j] = Ld[j][lane];
+    const double dl = 1.0 / Ld[lane][lane];
     const double tot = ((sacc[0][lane] + sacc[1][lane]) + sacc[2][lane]) + sacc[3][lane];
     double val = (lane < cols) ? (zin[c0 + lane] - tot) : 0.0;
     double mine = 0.0;
+#pragma unroll
     for (int j = TB - 1; j >= 0; --j) {
-      const double yj = __shfl(val, j, 64) / Ld[j][j];
+      const double yj = readlane_d(val, j) * readlane_d(dl, j);
       if (lane == j) mine = yj;
-      if (lane < j) val -= Ld[j][lane] * yj;
+      if (lane < j) val -= Lc[j] * yj;
     }
     if (lane < cols) y[c0 + lane] = mine;
-    __threadfence();
-    if (lane == 0) __hip_atomic_store(&flags[rb], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) publish(&flags[rb]);
   }
 }
 

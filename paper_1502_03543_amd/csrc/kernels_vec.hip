@@ -109,20 +109,23 @@ __global__ void k_dual_resid(long n, const double* P, int nchunks, const double*
   rd[j] = c[j] - g - s[j];
 }
 
-// D = S^-1 X (Section 5) and w = d o r_d.
+// D = S^-1 X (Section 5) and w = d o r_d; sd = sqrt(d) in FP32 when asked
+// (the column scaling of the FP32 normal matrix).
 __global__ void k_prep(long n, const double* x, const double* s, const double* rd, double* d,
-                       double* w) {
+                       double* w, float* sd) {
   const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (j >= n) return;
   const double dj = x[j] / s[j];
   d[j] = dj;
   w[j] = dj * rd[j];
+  if (sd) sd[j] = (float)sqrt(dj);
 }
 
-// out = b + A w, one wavefront per row of the row-major A.
+// out = b + sign * A w, one wavefront per row of the row-major A.
 __global__ __launch_bounds__(256) void k_gemv_n(long m, long n, const double* __restrict__ A,
                                                 const double* __restrict__ w,
-                                                const double* __restrict__ b, double* out) {
+                                                const double* __restrict__ b, double sign,
+                                                double* out) {
   const long row = blockIdx.x * 4L + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= m) return;
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(256) void k_gemv_n(long m, long n, const double* __
     for (long j = lane; j < n; j += 64) acc += a[j] * w[j];
   }
   acc = wave_sum(acc);
-  if (lane == 0) out[row] = b[row] + acc;
+  if (lane == 0) out[row] = b[row] + sign * acc;
 }
 
 // Partial transposed products over chunks of kGemvRows rows:
@@ -360,6 +363,86 @@ __global__ void k_copy(double* dst, const double* src, long count) {
   if (i < count) dst[i] = src[i];
 }
 
+// ---- mixed precision helpers ----------------------------------------------
+
+__global__ void k_to_f32(long count, const double* __restrict__ src, float* __restrict__ dst) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = (float)src[i];
+}
+
+// Squared column norms of A (once at setup): c_j = sum_i A_ij^2, so that
+// trace(A D A^T) = sum_j d_j c_j.
+__global__ __launch_bounds__(256) void k_colsq(long m, long n, const double* __restrict__ A,
+                                               double* out) {
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double acc = 0;
+  for (long i = 0; i < m; ++i) {
+    const double a = A[i * n + j];
+    acc += a * a;
+  }
+  out[j] = acc;
+}
+
+// v_j = d_j * sum_chunks P[chunk][j]  (d o A^T dy for the matrix-free residual)
+__global__ void k_scale_partials(long n, const double* P, int nchunks, const double* d,
+                                 double* v) {
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double g = 0;
+  for (int k = 0; k < nchunks; ++k) g += P[(long)k * n + j];
+  v[j] = d[j] * g;
+}
+
+__global__ void k_axpy(long count, const double* __restrict__ x, double* __restrict__ y) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < count) y[i] += x[i];
+}
+
+// Refinement test quantities: out[0] = ||r||_inf, out[1] = ||dy||_inf,
+// out[2] = trace(M) = sum_j d_j c_j (one workgroup, fixed order).
+__global__ __launch_bounds__(256) void k_refine_norms(long m, long n, const double* r,
+                                                      const double* dy, const double* d,
+                                                      const double* colsq, double* out) {
+  __shared__ double sh[4];
+  __shared__ double smax[2][4];
+  double rn = 0, yn = 0, tr = 0;
+  for (long i = threadIdx.x; i < m; i += blockDim.x) {
+    rn = fmax(rn, fabs(r[i]));
+    yn = fmax(yn, fabs(dy[i]));
+  }
+  for (long j = threadIdx.x; j < n; j += blockDim.x) tr += d[j] * colsq[j];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    rn = fmax(rn, __shfl_xor(rn, o, 64));
+    yn = fmax(yn, __shfl_xor(yn, o, 64));
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    smax[0][w] = rn;
+    smax[1][w] = yn;
+  }
+  const double t = block_sum(tr, sh);
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      a = fmax(a, smax[0][k]);
+      b = fmax(b, smax[1][k]);
+    }
+    out[0] = a;
+    out[1] = b;
+    out[2] = t;
+  }
+}
+
+// FP32 factor (row-major lower, ld32) widened into the FP64 buffer (ld64).
+__global__ void k_lower_f32_to_f64(long m, const float* __restrict__ L32, long ld32,
+                                   double* __restrict__ L64, long ld64) {
+  const long i = blockIdx.y;
+  for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j <= i; j += (long)gridDim.x * blockDim.x)
+    L64[i * ld64 + j] = (double)L32[i * ld32 + j];
+}
+
 }  // namespace
 
 void launch_check_inputs(hipStream_t st, long m, long n, const double* A, const double* b,
@@ -387,13 +470,13 @@ void launch_dual_resid(hipStream_t st, long m, long n, const double* P, int nchu
 }
 
 void launch_prep(hipStream_t st, long n, const double* x, const double* s, const double* rd,
-                 double* d, double* w) {
-  hipLaunchKernelGGL(k_prep, dim3(cdiv(n, kT)), dim3(kT), 0, st, n, x, s, rd, d, w);
+                 double* d, double* w, float* sd) {
+  hipLaunchKernelGGL(k_prep, dim3(cdiv(n, kT)), dim3(kT), 0, st, n, x, s, rd, d, w, sd);
 }
 
 void launch_gemv_n(hipStream_t st, long m, long n, const double* A, const double* w,
-                   const double* b, double* out) {
-  hipLaunchKernelGGL(k_gemv_n, dim3(cdiv(m, 4)), dim3(256), 0, st, m, n, A, w, b, out);
+                   const double* b, double* out, double sign) {
+  hipLaunchKernelGGL(k_gemv_n, dim3(cdiv(m, 4)), dim3(256), 0, st, m, n, A, w, b, sign, out);
 }
 
 int gemv_t_chunks(long m) { return cdiv(m, kGemvRows); }
@@ -443,6 +526,36 @@ void launch_gap(hipStream_t st, long n, const double* x, const double* s, double
 void launch_copy(hipStream_t st, double* dst, const double* src, long count) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_copy, dim3(cdiv(count, kT)), dim3(kT), 0, st, dst, src, count);
+}
+
+void launch_to_f32(hipStream_t st, long count, const double* src, float* dst) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_to_f32, dim3(cdiv(count, kT)), dim3(kT), 0, st, count, src, dst);
+}
+
+void launch_colsq(hipStream_t st, long m, long n, const double* A, double* out) {
+  hipLaunchKernelGGL(k_colsq, dim3(cdiv(n, 256)), dim3(256), 0, st, m, n, A, out);
+}
+
+void launch_scale_partials(hipStream_t st, long n, const double* P, int nchunks, const double* d,
+                           double* v) {
+  hipLaunchKernelGGL(k_scale_partials, dim3(cdiv(n, kT)), dim3(kT), 0, st, n, P, nchunks, d, v);
+}
+
+void launch_axpy(hipStream_t st, long count, const double* x, double* y) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_axpy, dim3(cdiv(count, kT)), dim3(kT), 0, st, count, x, y);
+}
+
+void launch_refine_norms(hipStream_t st, long m, long n, const double* r, const double* dy,
+                         const double* d, const double* colsq, double* out) {
+  hipLaunchKernelGGL(k_refine_norms, dim3(1), dim3(256), 0, st, m, n, r, dy, d, colsq, out);
+}
+
+void launch_lower_f32_to_f64(hipStream_t st, long m, const float* L32, long ld32, double* L64,
+                             long ld64) {
+  const int bx = m > 256 ? cdiv(m, 256) : 1;
+  hipLaunchKernelGGL(k_lower_f32_to_f64, dim3(bx, m), dim3(256), 0, st, m, L32, ld32, L64, ld64);
 }
 
 }  // namespace pdas

@@ -50,9 +50,10 @@ void launch_iter_begin(hipStream_t st, DevInfo* info, int* trsv_sync, int nblk);
 void launch_dual_resid(hipStream_t st, long m, long n, const double* P, int nchunks,
                        const double* c, const double* s, double* rd);
 void launch_prep(hipStream_t st, long n, const double* x, const double* s, const double* rd,
-                 double* d, double* w);
+                 double* d, double* w, float* sd = nullptr);
+// out = b + sign * A w
 void launch_gemv_n(hipStream_t st, long m, long n, const double* A, const double* w,
-                   const double* b, double* out);
+                   const double* b, double* out, double sign = 1.0);
 void launch_gemv_t(hipStream_t st, long m, long n, const double* A, const double* v1,
                    const double* v2, double* P1, double* P2);
 int gemv_t_chunks(long m);
@@ -73,6 +74,16 @@ void launch_finish(hipStream_t st, int nparts, const double* gap_part, const int
 void launch_gap(hipStream_t st, long n, const double* x, const double* s, double* gap_part,
                 double* out);
 void launch_copy(hipStream_t st, double* dst, const double* src, long count);
+// mixed precision helpers
+void launch_to_f32(hipStream_t st, long count, const double* src, float* dst);
+void launch_colsq(hipStream_t st, long m, long n, const double* A, double* out);
+void launch_scale_partials(hipStream_t st, long n, const double* P, int nchunks, const double* d,
+                           double* v);
+void launch_axpy(hipStream_t st, long count, const double* x, double* y);
+void launch_refine_norms(hipStream_t st, long m, long n, const double* r, const double* dy,
+                         const double* d, const double* colsq, double* out);
+void launch_lower_f32_to_f64(hipStream_t st, long m, const float* L32, long ld32, double* L64,
+                             long ld64);
 
 // --- normal matrix (kernels_syrk.hip) --------------------------------------
 // C (row-major lower, ldc) = X diag(w) X^T (w may be null) or, when sub,
@@ -83,11 +94,19 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
                      hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 size_t syrk_part_elems(int mm, int tile, int splits);
 void syrk_choose(int mm, int K, int* tile, int* splits);
+// FP32: C32 = (X diag(w))(X diag(w))^T (w = sqrt(d), may be null) or C32 -= X X^T.
+// Returns false (nothing launched) when K or the rows are not 4-aligned.
+bool launch_syrk_f32(hipStream_t st, int mm, int K, const float* X, long ldx, const float* w,
+                     float* C, long ldc, bool sub, int splits, float* part,
+                     hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+size_t syrk_part_elems_f32(int mm, int splits);
+void syrk_choose_f32(int mm, int K, int* splits);
 
 // --- Cholesky (kernels_chol.hip) -------------------------------------------
 // In-place lower Cholesky of M (row-major, ld), m x m; failures recorded in info.
 void launch_potrf_f64(hipStream_t st, int m, double* M, long ld, DevInfo* info, double* part,
                       size_t part_elems);
+void launch_potrf_f32(hipStream_t st, int m, float* M, long ld, DevInfo* info);
 
 // --- triangular solves (kernels_trsv.hip) ----------------------------------
 // z = L^-1 r (fwd) then y = L^-T z (bwd); L row-major lower with ld.
@@ -96,5 +115,76 @@ void launch_trsv_fwd(hipStream_t st, int m, const double* L, long ld, const doub
                      int* sync, DevInfo* info);
 void launch_trsv_bwd(hipStream_t st, int m, const double* L, long ld, const double* z, double* y,
                      int* sync, DevInfo* info);
+
+// --- reverse mode (kernels_adjoint.hip) -------------------------------------
+void launch_zero(hipStream_t st, double* p, long count);
+void launch_adj_tbar(hipStream_t st, long m, long n, const double* xb, const double* dx,
+                     const double* sb, const double* ds, const double* yb, const double* dy,
+                     double* part, double* out);
+void launch_adj_a(hipStream_t st, long m, long n, double alpha, const DevInfo* info,
+                  const double* tbar, const double* x, const double* s, const double* d,
+                  const double* dx, const double* ds, double* xb, double* sb, const double* yb,
+                  double* dsb, double* db, double* dyb);
+void launch_adj_b(hipStream_t st, long m, long n, const double* P, int nchunks, const double* g,
+                  const double* rd, const double* d, const double* x, const double* s,
+                  const double* lam, const double* dsb, double* db, double* xb, double* sb,
+                  double* cb, double* rdb, double* bb, double* v1, double* v2, double* v3);
+void launch_rank3(hipStream_t st, long m, long n, double* Ab, const double* u1, const double* v1,
+                  const double* u2, const double* v2, const double* u3, const double* v3);
+
+// --- batched solver (kernels_batch.hip) ------------------------------------
+struct BatchLP {
+  int m, n, ldm, pad;
+  long a_off;     // element offset of A_i in the packed matrices
+  long vm, vn;    // element offsets of the m- and n-vectors of LP i
+  long M_off;     // element offset of M_i (ldm x m) in the matrix pool
+  long tape_off;  // element offset of LP i's tape
+};
+
+struct BatchState {
+  int status;     // lp_status; LP_OK while active
+  int iters;      // directions taken
+  int cur;        // which iterate buffer holds the current iterate
+  int pad;
+  double gap;     // x^T s of the current iterate
+  double last_psi, last_t;
+  long long last_argmax;
+};
+
+struct BatchArgs {
+  int count;
+  int max_iter;
+  double alpha, tol;
+  const BatchLP* lps;
+  const int* order;     // processing order (largest m^2 n first)
+  BatchState* state;
+  const double* A;      // caller's packed matrices (offsets a_off)
+  const double* b;      // workspace copies, packed by vm / vn
+  const double* c;
+  double* x[2];
+  double* y[2];
+  double* s[2];
+  double* rd[2];
+  double *d, *w, *g, *gy, *dx, *ds, *rhs, *z, *dy, *M;
+  double* tape;
+  int tape_cap;
+  int* queue;
+  int* active;
+};
+
+// Adjoint pools of a batch (packed like the forward vectors; Abar like A).
+struct BatchAdj {
+  double *xb, *yb, *sb, *dsb, *db, *dyb, *lam, *h, *rdb, *bbar, *cbar;
+  double* Abar;  // caller's output, may be null
+  int* err;
+};
+
+__global__ void k_batch_iter(BatchArgs a);
+void launch_batch_iter(hipStream_t st, const BatchArgs& args, int grid);
+void launch_batch_backward(hipStream_t st, const BatchArgs& args, const BatchAdj& adj, int k,
+                           int grid);
+void launch_batch_setup(hipStream_t st, int count, const BatchLP* lps, BatchState* state,
+                        const double* Ap, const double* c, const double* x, const double* y,
+                        const double* s, double* rd);
 
 }  // namespace pdas

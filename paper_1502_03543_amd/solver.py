@@ -40,7 +40,7 @@ def workspace(nbytes: int, device) -> tuple[torch.Tensor, int]:
 
 
 def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6,
-            refine_tol=1e-12, refine_max=5, profile=False) -> capi.lp_options:
+            refine_tol=2.0 ** -46, refine_max=5, profile=False) -> capi.lp_options:
     o = capi.lp_options()
     capi.lp_options_default(C.byref(o))
     o.alpha = float(alpha)
@@ -99,6 +99,19 @@ class LP:
         s = torch.empty(self.n, dtype=torch.float64, device=self.device)
         capi.check(capi.lp_get_iterate(self.h, _p(x), _p(y), _p(s)), "lp_get_iterate")
         return x, y, s
+
+    def tape(self, K):
+        """The first K recorded start iterates as a (K, 2n + m) numpy array of
+        rows [x | y | s]."""
+        import numpy as np
+        rows = []
+        for k in range(K):
+            x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            y = torch.empty(self.m, dtype=torch.float64, device=self.device)
+            s = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            capi.check(capi.lp_tape_row(self.h, k, _p(x), _p(y), _p(s)), "lp_tape_row")
+            rows.append(torch.cat([x, y, s]).cpu().numpy())
+        return np.stack(rows)
 
     def direction(self):
         """(dx, dy, ds) of the most recent iterate() call."""
@@ -184,3 +197,164 @@ def chol_solve(L, r):
                "lp_chol_solve")
     torch.cuda.current_stream().synchronize()
     return dy
+
+
+class Batch:
+    """Many LPs solved together (lp_batch_setup ... lp_batch_destroy).
+
+    ``problems`` is a list of objects with numpy fields A (m_i x n_i), b, c,
+    x0, y0, s0; they are packed on the host, uploaded once, and solved by the
+    batched kernel.  FP64."""
+
+    def __init__(self, problems, alpha=0.95, tape_capacity=0, device="cuda"):
+        import numpy as np
+
+        self.count = len(problems)
+        self.m = np.array([p.A.shape[0] for p in problems], dtype=np.int64)
+        self.n = np.array([p.A.shape[1] for p in problems], dtype=np.int64)
+        mn = self.m * self.n
+        self.a_off = np.concatenate([[0], np.cumsum(mn)[:-1]]).astype(np.int64)
+        self.v_off_m = np.concatenate([[0], np.cumsum(self.m)[:-1]]).astype(np.int64)
+        self.v_off_n = np.concatenate([[0], np.cumsum(self.n)[:-1]]).astype(np.int64)
+        cat = lambda k: np.ascontiguousarray(
+            np.concatenate([np.asarray(getattr(p, k), dtype=np.float64).ravel() for p in problems]))
+        dev = torch.device(device)
+        self.A = torch.from_numpy(cat("A")).to(dev)
+        self.b = torch.from_numpy(cat("b")).to(dev)
+        self.c = torch.from_numpy(cat("c")).to(dev)
+        self.x0 = torch.from_numpy(cat("x0")).to(dev)
+        self.y0 = torch.from_numpy(cat("y0")).to(dev)
+        self.s0 = torch.from_numpy(cat("s0")).to(dev)
+        self.device = dev
+        self.opts = options(alpha=alpha, tape_capacity=tape_capacity)
+        I64 = C.c_int64 * self.count
+        self._m, self._n = I64(*self.m), I64(*self.n)
+        self._aoff, self._vom, self._von = I64(*self.a_off), I64(*self.v_off_m), I64(*self.v_off_n)
+        size = C.c_size_t(0)
+        capi.check(capi.lp_batch_workspace_size(self.count, self._m, self._n, C.byref(self.opts),
+                                                C.byref(size)), "lp_batch_workspace_size")
+        self._ws, addr = workspace(size.value, dev)
+        h = C.c_void_p()
+        st = capi.lp_batch_setup(C.byref(h), self.count, self._m, self._n, _p(self.A), self._aoff,
+                                 _p(self.b), _p(self.c), _p(self.x0), _p(self.y0), _p(self.s0),
+                                 self._vom, self._von, C.byref(self.opts), C.c_void_p(addr),
+                                 size.value, _stream())
+        capi.check(st, "lp_batch_setup")
+        self.h = h
+
+    def solve(self, tol=1e-8, max_iter=200):
+        import numpy as np
+
+        stat = (C.c_int32 * self.count)()
+        its = (C.c_int32 * self.count)()
+        nconv = C.c_int32(0)
+        capi.check(capi.lp_batch_solve(self.h, float(tol), int(max_iter), stat, its,
+                                       C.byref(nconv)), "lp_batch_solve")
+        return dict(status=np.array(stat[:]), iters=np.array(its[:]), n_converged=nconv.value)
+
+    def iterates(self):
+        """List of (x, y, s) numpy arrays, one per LP."""
+        sn, sm = int(self.n.sum()), int(self.m.sum())
+        x = torch.empty(sn, dtype=torch.float64, device=self.device)
+        y = torch.empty(sm, dtype=torch.float64, device=self.device)
+        s = torch.empty(sn, dtype=torch.float64, device=self.device)
+        capi.check(capi.lp_batch_get_iterate(self.h, _p(x), _p(y), _p(s)), "lp_batch_get_iterate")
+        torch.cuda.current_stream().synchronize()
+        x, y, s = x.cpu().numpy(), y.cpu().numpy(), s.cpu().numpy()
+        out = []
+        for i in range(self.count):
+            jn, jm = self.v_off_n[i], self.v_off_m[i]
+            out.append((x[jn:jn + self.n[i]], y[jm:jm + self.m[i]], s[jn:jn + self.n[i]]))
+        return out
+
+    def tape(self, K):
+        """Per LP, a (K, 2n + m) numpy array of recorded start iterates."""
+        import numpy as np
+        sn, sm = int(self.n.sum()), int(self.m.sum())
+        per = [[] for _ in range(self.count)]
+        for k in range(K):
+            x = torch.empty(sn, dtype=torch.float64, device=self.device)
+            y = torch.empty(sm, dtype=torch.float64, device=self.device)
+            s = torch.empty(sn, dtype=torch.float64, device=self.device)
+            capi.check(capi.lp_batch_tape_row(self.h, k, _p(x), _p(y), _p(s)), "lp_batch_tape_row")
+            x, y, s = x.cpu().numpy(), y.cpu().numpy(), s.cpu().numpy()
+            for i in range(self.count):
+                jn, jm = self.v_off_n[i], self.v_off_m[i]
+                per[i].append(np.concatenate([x[jn:jn + self.n[i]], y[jm:jm + self.m[i]],
+                                              s[jn:jn + self.n[i]]]))
+        return [np.stack(r) for r in per]
+
+    def backward(self, xbar, ybar=None, sbar=None):
+        """Packed gradients (dict A, b, c, x0, y0, s0) of a loss on the final
+        iterates; xbar (and ybar, sbar) packed like iterates()."""
+        dev = self.device
+        f = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+        sn, sm = int(self.n.sum()), int(self.m.sum())
+        out = dict(A=torch.zeros_like(self.A), b=f(sm), c=f(sn), x0=f(sn), y0=f(sm), s0=f(sn))
+        xbar = xbar.contiguous().to(torch.float64)
+        ybar = None if ybar is None else ybar.contiguous().to(torch.float64)
+        sbar = None if sbar is None else sbar.contiguous().to(torch.float64)
+        st = capi.lp_batch_backward(self.h, _p(xbar), _p(ybar), _p(sbar), _p(out["A"]),
+                                    _p(out["b"]), _p(out["c"]), _p(out["x0"]), _p(out["y0"]),
+                                    _p(out["s0"]))
+        capi.check(st, "lp_batch_backward")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            capi.lp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _lp_backward(lp, xbar, ybar=None, sbar=None):
+    """Gradients of a loss on the final iterate with respect to the setup
+    inputs (lp_backward).  Returns dict A, b, c, x0, y0, s0 of tensors."""
+    m, n, dev = lp.m, lp.n, lp.device
+    out = dict(A=torch.empty((m, n), dtype=torch.float64, device=dev),
+               b=torch.empty(m, dtype=torch.float64, device=dev),
+               c=torch.empty(n, dtype=torch.float64, device=dev),
+               x0=torch.empty(n, dtype=torch.float64, device=dev),
+               y0=torch.empty(m, dtype=torch.float64, device=dev),
+               s0=torch.empty(n, dtype=torch.float64, device=dev))
+    xbar = xbar.contiguous().to(torch.float64)
+    ybar = None if ybar is None else ybar.contiguous().to(torch.float64)
+    sbar = None if sbar is None else sbar.contiguous().to(torch.float64)
+    st = capi.lp_backward(lp.h, _p(xbar), _p(ybar), _p(sbar), _p(out["A"]), _p(out["b"]),
+                          _p(out["c"]), _p(out["x0"]), _p(out["y0"]), _p(out["s0"]))
+    capi.check(st, "lp_backward")
+    return out
+
+
+LP.backward = _lp_backward
+
+
+class PDASFixedK(torch.autograd.Function):
+    """x_K after exactly K Section 3 steps from (x0, y0, s0), differentiable with
+    respect to A, b, c, x0, y0, s0 (the reverse sweep recomputes every step and
+    reuses its Cholesky factor).  The forward stops early only at a psi == 1
+    step or an error, which raise."""
+
+    @staticmethod
+    def forward(ctx, A, b, c, x0, y0, s0, K, alpha=0.9):
+        lp = LP(A.detach().contiguous(), b.detach().contiguous(), c.detach().contiguous(),
+                x0.detach().contiguous(), y0.detach().contiguous(), s0.detach().contiguous(),
+                alpha=alpha, tape_capacity=int(K))
+        res = lp.solve(0.0, int(K))
+        if res["status"] != capi.LP_MAX_ITER or res["iters"] != int(K):
+            raise RuntimeError(f"fixed-K run stopped early: {capi.status_string(res['status'])}")
+        x, y, s = lp.iterate_values()
+        ctx.lp = lp
+        ctx.keep = (A, b, c, x0, y0, s0)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        g = ctx.lp.backward(gx)
+        ctx.lp.close()
+        return g["A"], g["b"], g["c"], g["x0"], g["y0"], g["s0"], None, None

@@ -1,0 +1,114 @@
+"""Reverse mode on the GPU (lp_backward, PDASFixedK) against the oracle's
+reverse mode on the same problem and against long-double central
+differences."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1502_03543_amd import capi, lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("gpu tests need a ROCm GPU")
+    capi.load()
+    return torch, torch.device("cuda:0")
+
+
+def _T(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+
+@pytest.mark.parametrize("m,n,K,seed", [(6, 20, 1, 0), (12, 40, 3, 1), (64, 256, 10, 2),
+                                        (100, 333, 8, 3)])
+def test_backward_matches_oracle(torch_dev, m, n, K, seed):
+    torch, dev = torch_dev
+    from paper_1502_03543_amd import solver
+    lp = lpgen.gen_lp(m, n, seed)
+    w = lpgen.loss_weights(n, seed)
+    T = [_T(torch, dev, v) for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
+    h = solver.LP(*T, alpha=0.9, tape_capacity=K)
+    res = h.solve(0.0, K)
+    assert res["status"] == capi.LP_MAX_ITER and res["iters"] == K
+    g = h.backward(_T(torch, dev, w))
+    # the oracle's reverse mode on the GPU's own recorded trajectory
+    st, go = oracle.backward(lp.A, lp.b, lp.c, 0.9, K, h.tape(K), w)
+    assert st == oracle.CONTINUE
+    for key, okey in (("A", "Abar"), ("b", "bbar"), ("c", "cbar"), ("x0", "x0bar"),
+                      ("y0", "y0bar"), ("s0", "s0bar")):
+        a = g[key].cpu().numpy()
+        o = go[okey]
+        scale = max(np.linalg.norm(o), 1e-12 * np.linalg.norm(go["x0bar"]))
+        rel = np.linalg.norm(a - o) / scale
+        print(key, rel)
+        assert rel <= 1e-6, (key, rel)
+
+
+def test_autograd_fd(torch_dev):
+    """torch.autograd through PDASFixedK against long-double central
+    differences (h = 1e-6) of w^T x_K, K = 2."""
+    torch, dev = torch_dev
+    from paper_1502_03543_amd import solver
+    m, n, K, seed = 8, 30, 2, 4
+    lp = lpgen.gen_lp(m, n, seed)
+    w = lpgen.loss_weights(n, seed)
+    T = [_T(torch, dev, v).requires_grad_(True) for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
+    xK = solver.PDASFixedK.apply(*T, K, 0.9)
+    loss = (xK * _T(torch, dev, w)).sum()
+    loss.backward()
+    rng = np.random.default_rng(0)
+    for t, key in zip(T, ("A", "b", "c", "x0", "y0", "s0")):
+        E = rng.standard_normal(tuple(t.shape))
+        _, lpl, *_ = oracle.forward_k(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.9, K, w,
+                                      {key: E}, 1e-6, precision="f80")
+        _, lmi, *_ = oracle.forward_k(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.9, K, w,
+                                      {key: E}, -1e-6, precision="f80")
+        fd = (lpl - lmi) / 2e-6
+        an = float((t.grad.cpu().numpy() * E).sum())
+        assert abs(an - fd) <= 1e-6 * max(abs(fd), 1e-2), (key, an, fd)
+
+
+def test_backward_without_tape_fails(torch_dev):
+    torch, dev = torch_dev
+    from paper_1502_03543_amd import solver
+    lp = lpgen.gen_lp(8, 24, 0)
+    T = [_T(torch, dev, v) for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
+    h = solver.LP(*T, alpha=0.9)
+    h.solve(0.0, 2)
+    with pytest.raises(RuntimeError, match="LP_ERR_NO_TAPE"):
+        h.backward(_T(torch, dev, np.ones(24)))
+
+
+def test_batch_backward_differentiable_config(torch_dev):
+    """64 LPs, m = 256, n = 1024, K = 30, alpha = 0.9, loss w^T x_K: the batched
+    reverse sweep against the oracle's reverse mode on the GPU's own tape for
+    4 LPs (norm-wise 1e-6 for Abar and bbar, the others reported)."""
+    torch, dev = torch_dev
+    from paper_1502_03543_amd import solver
+    K = 30
+    lps = [lpgen.gen_lp(256, 1024, i) for i in range(64)]
+    ws = [lpgen.loss_weights(1024, i) for i in range(64)]
+    bt = solver.Batch(lps, alpha=0.9, tape_capacity=K)
+    res = bt.solve(0.0, K)
+    assert all(capi.status_string(s) == "LP_MAX_ITER" for s in res["status"]), res["status"]
+    assert all(it == K for it in res["iters"])
+    g = bt.backward(torch.from_numpy(np.concatenate(ws)).to(dev))
+    tapes = bt.tape(K)
+    Ag = g["A"].cpu().numpy()
+    for i in (0, 17, 40, 63):
+        lp = lps[i]
+        st, go = oracle.backward(lp.A, lp.b, lp.c, 0.9, K, tapes[i], ws[i])
+        assert st == oracle.CONTINUE
+        a0 = int(bt.a_off[i])
+        Ai = Ag[a0:a0 + 256 * 1024].reshape(256, 1024)
+        bi = g["b"].cpu().numpy()[bt.v_off_m[i]:bt.v_off_m[i] + 256]
+        ci = g["c"].cpu().numpy()[bt.v_off_n[i]:bt.v_off_n[i] + 1024]
+        ra = np.linalg.norm(Ai - go["Abar"]) / np.linalg.norm(go["Abar"])
+        rb = np.linalg.norm(bi - go["bbar"]) / np.linalg.norm(go["bbar"])
+        rc = np.linalg.norm(ci - go["cbar"]) / np.linalg.norm(go["cbar"])
+        print(f"LP {i}: Abar {ra:.1e} bbar {rb:.1e} cbar {rc:.1e}")
+        assert ra <= 1e-6 and rb <= 1e-6, (i, ra, rb)

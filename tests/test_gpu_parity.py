@@ -126,7 +126,8 @@ def test_iteration_parity(torch_dev, m, n, seed):
         res = np.linalg.norm(it.rhs - it.M @ dyg)
         bound = 10 * U * (n * np.linalg.norm(absA @ (it.d * (absA.T @ np.abs(dyg))))
                           + m * np.linalg.norm(it.M, 2) * np.linalg.norm(dyg)
-                          + n * np.linalg.norm(np.abs(lp.b) + absA @ (it.d * np.abs(it.r_d))))
+                          + n * np.linalg.norm(np.abs(lp.b) + absA @ (it.d * (
+                              np.abs(lp.c) + absA.T @ np.abs(y) + s))))
         assert res <= bound, (k, res, bound)
         assert abs(info["psi"] - it.psi) <= tol * it.psi, (k, info["psi"], it.psi)
         if abs(info["psi"] - it.psi) <= 1e-14 * it.psi:
