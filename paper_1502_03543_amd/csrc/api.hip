@@ -46,6 +46,7 @@ struct lp_handle {
   double *dx = nullptr, *ds = nullptr, *g = nullptr, *gy = nullptr;
   // normal matrix / factor (row-major lower, ld ldm)
   double* M = nullptr;
+  double* diag = nullptr;  // diagonal blocks of the factor (scratch of the Cholesky)
   long ldm = 0;
   int syrk_tile = 128, syrk_splits = 1;
   double* syrk_part = nullptr;
@@ -124,6 +125,7 @@ void carve(lp_handle* h, Carver& cv) {
   h->gy = cv.take<double>(n);
   h->ldm = (m + 7) / 8 * 8;
   h->M = cv.take<double>((size_t)h->ldm * m);
+  h->diag = cv.take<double>(potrf_diag_elems(m));
   syrk_choose((int)m, (int)n, &h->syrk_tile, &h->syrk_splits);
   h->syrk_part_n = syrk_part_elems((int)m, h->syrk_tile, h->syrk_splits);
   h->syrk_part = h->syrk_part_n ? cv.take<double>(h->syrk_part_n) : nullptr;
@@ -352,7 +354,7 @@ static void solve_fp64(lp_handle* h) {
                   h->profiling ? h->ev[lp_handle::EV_SYRKK0] : nullptr,
                   h->profiling ? h->ev[lp_handle::EV_SYRKK1] : nullptr);
   mark(h, lp_handle::EV_SYRK1);
-  launch_potrf_f64(s, (int)m, h->M, h->ldm, h->info, nullptr, 0);
+  launch_potrf_f64(s, (int)m, h->M, h->ldm, h->info, h->diag);
   mark(h, lp_handle::EV_CHOL1);
   launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
   launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
@@ -390,7 +392,7 @@ static bool solve_mixed(lp_handle* h, bool* ok) {
                        h->profiling ? h->ev[lp_handle::EV_SYRKK1] : nullptr))
     return true;  // shapes the FP32 kernel does not take: FP64
   mark(h, lp_handle::EV_SYRK1);
-  launch_potrf_f32(s, (int)m, h->M32, h->ld32, h->info);
+  launch_potrf_f32(s, (int)m, h->M32, h->ld32, h->info, reinterpret_cast<float*>(h->diag));
   mark(h, lp_handle::EV_CHOL1);
   DevInfo di;
   if (!read_info(h, &di)) return false;
@@ -622,7 +624,7 @@ lp_status lp_backward(lp_handle* h, const double* xbar_K, const double* ybar_K,
     launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
     launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->d, h->M, h->ldm, false, h->syrk_tile,
                     h->syrk_splits, h->syrk_part);
-    launch_potrf_f64(s, (int)m, h->M, h->ldm, h->info, nullptr, 0);
+    launch_potrf_f64(s, (int)m, h->M, h->ldm, h->info, h->diag);
     launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
     launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
     launch_gemv_t(s, m, n, h->A, h->dy, h->by, h->P1, h->P2);
@@ -700,6 +702,7 @@ struct Blocks {
   int* sync = nullptr;
   DevInfo* info = nullptr;
   double* z = nullptr;
+  double* diag = nullptr;
 };
 
 void carve_blocks(long m, long n, Carver& cv, Blocks& b) {
@@ -707,6 +710,7 @@ void carve_blocks(long m, long n, Carver& cv, Blocks& b) {
   b.part_n = syrk_part_elems((int)m, b.tile, b.splits);
   b.part = b.part_n ? cv.take<double>(b.part_n) : nullptr;
   b.sync = cv.take<int>(4 + 2 * cdiv(m, kTB));
+  b.diag = cv.take<double>(potrf_diag_elems(m));
   b.info = cv.take<DevInfo>(1);
   b.z = cv.take<double>(m);
 }
@@ -754,7 +758,7 @@ lp_status lp_cholesky(int64_t m, double* M, int64_t ldm, void* workspace, size_t
   if (st != LP_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   launch_iter_begin(s, b.info, b.sync, cdiv(m, kTB));
-  launch_potrf_f64(s, (int)m, M, ldm, b.info, nullptr, 0);
+  launch_potrf_f64(s, (int)m, M, ldm, b.info, b.diag);
   DevInfo di;
   hipError_t e = hipMemcpyAsync(&di, b.info, sizeof(di), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

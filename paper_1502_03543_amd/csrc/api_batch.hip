@@ -1,8 +1,7 @@
 // C ABI of the batched solver: many independent LPs, each advanced by the
-// Section 3 iteration, one kernel launch per iteration for the whole batch.
-// Iterations are captured into a hipGraph (a queue-reset node and the batch
-// kernel per iteration, several iterations per graph) and replayed until no
-// LP remains active.  The library allocates no device memory: everything is
+// Section 3 iteration.  One iteration of the whole batch is a fixed sequence
+// of launches (see kernels_batch.hip); several iterations are captured into
+// one hipGraph and replayed until no LP remains active.  The library allocates no device memory: everything is
 // carved from the caller's workspace.
 #include <algorithm>
 #include <climits>
@@ -131,7 +130,6 @@ struct lp_batch {
   long sum_m = 0, sum_n = 0;
   BatchArgs args{};
   BatchLP* lps = nullptr;
-  int* order = nullptr;
   BatchState* state = nullptr;
   double* bufptrs = nullptr;  // device copies of the iterate buffer pointers
   int* flags = nullptr;
@@ -139,7 +137,7 @@ struct lp_batch {
   long long* uvn = nullptr;
   BatchAdj adj{};             // reverse-sweep pools (with a tape)
   int max_iters_run = 0;
-  int grid = 1;
+  int max_m = 0;
 };
 
 namespace {
@@ -154,7 +152,7 @@ bool batch_shapes_ok(int32_t count, const int64_t* m, const int64_t* n) {
 void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
   const int count = h->count;
   h->lps_h.resize(count);
-  long vm = 0, vn = 0, moff = 0, toff = 0;
+  long vm = 0, vn = 0, moff = 0, toff = 0, doff = 0;
   const int tape_cap = h->opt.tape_capacity > 0 ? h->opt.tape_capacity : 0;
   for (int i = 0; i < count; ++i) {
     BatchLP& P = h->lps_h[i];
@@ -167,17 +165,18 @@ void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
     P.vn = vn;
     P.M_off = moff;
     P.tape_off = toff;
+    P.diag_off = doff;
+    doff += potrf_diag_elems(P.m);
     vm += P.m;
     vn += P.n;
     moff += (long)P.ldm * P.m;
-    toff += (long)(tape_cap + 1) * (2 * P.n + P.m);
+    toff += (long)(tape_cap + 1) * (3 * P.n + P.m);
   }
   h->sum_m = vm;
   h->sum_n = vn;
   BatchArgs& a = h->args;
   a.count = count;
   h->lps = cv.take<BatchLP>(count);
-  h->order = cv.take<int>(count);
   h->state = cv.take<BatchState>(count);
   h->flags = cv.take<int>(count);
   h->uvm = cv.take<long long>(count);
@@ -200,10 +199,15 @@ void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
   a.z = cv.take<double>(vm);
   a.dy = cv.take<double>(vm);
   a.M = cv.take<double>(moff);
+  a.diag = cv.take<double>(doff);
   a.tape_cap = tape_cap;
   a.tape = tape_cap ? cv.take<double>(toff) : nullptr;
-  a.queue = cv.take<int>(1);
   a.active = cv.take<int>(1);
+  a.go = cv.take<int>(count);
+  a.fail = cv.take<int>(count);
+  a.minp = cv.take<unsigned long long>(count);
+  a.psi = cv.take<double>(count);
+  a.arg = cv.take<long long>(count);
   h->bufptrs = cv.take<double>(6);  // x[2], y[2], s[2] pointers for get_iterate
   if (tape_cap) {
     BatchAdj& g = h->adj;
@@ -272,24 +276,15 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
   BatchArgs& a = h->args;
   a.A = A_packed;
   a.lps = h->lps;
-  a.order = h->order;
   a.state = h->state;
   a.alpha = h->opt.alpha;
-  // largest m^2 n first (longest-processing-time order)
-  std::vector<int> order(count);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int p, int q) {
-    const double cp = (double)m[p] * m[p] * n[p], cq = (double)m[q] * m[q] * n[q];
-    return cp > cq;
-  });
+  for (int i = 0; i < count; ++i) h->max_m = std::max(h->max_m, (int)m[i]);
   hipStream_t s = h->st;
   std::vector<long long> uvm(v_off_m, v_off_m + count), uvn(v_off_n, v_off_n + count);
   long long* d_uvm = h->uvm;
   long long* d_uvn = h->uvn;
   hipError_t e =
       hipMemcpyAsync(h->lps, h->lps_h.data(), sizeof(BatchLP) * count, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(h->order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_uvm, uvm.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -323,10 +318,6 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
                      h->state);
   launch_batch_setup(s, count, h->lps, h->state, A_packed, a.c, a.x[0], a.y[0], a.s[0],
                      a.rd[0]);
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess)
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  h->grid = std::min(count, 2 * cus);
   e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
@@ -353,7 +344,7 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
   if (s != nullptr) {
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      for (int k = 0; k < kItersPerGraph; ++k) launch_batch_iter(s, a, h->grid);
+      for (int k = 0; k < kItersPerGraph; ++k) launch_batch_step(s, a, h->max_m, -1, nullptr);
       e = hipStreamEndCapture(s, &graph);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -364,7 +355,7 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
     if (exec) {
       e = hipGraphLaunch(exec, s);
     } else {
-      for (int k = 0; k < kItersPerGraph; ++k) launch_batch_iter(s, a, h->grid);
+      for (int k = 0; k < kItersPerGraph; ++k) launch_batch_step(s, a, h->max_m, -1, nullptr);
       e = hipGetLastError();
     }
     int active = 0;
@@ -423,7 +414,7 @@ lp_status lp_batch_backward(lp_batch* h, const double* xbar_K, const double* yba
   launch_fill_i32(s, g.err, 0, 1);
   if (Abar) hipLaunchKernelGGL(k_batch_zero_mats, dim3(64, h->count), dim3(256), 0, s, h->count,
                                h->lps, Abar);
-  for (int k = h->max_iters_run - 1; k >= 0; --k) launch_batch_backward(s, a, g, k, h->grid);
+  for (int k = h->max_iters_run - 1; k >= 0; --k) launch_batch_step(s, a, h->max_m, k, &g);
   if (x0bar) launch_copy(s, x0bar, g.xb, h->sum_n);
   if (y0bar) launch_copy(s, y0bar, g.yb, h->sum_m);
   if (s0bar) launch_copy(s, s0bar, g.sb, h->sum_n);

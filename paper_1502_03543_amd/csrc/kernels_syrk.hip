@@ -47,26 +47,23 @@ __device__ inline int lidx(int row, int k) {
 // R, Q: wavefront tile (4R) x (16Q); KC: K per stage; SCALE: multiply the row
 // operand by w[k] while staging; VEC: 16-byte loads (X rows and w 16-byte
 // aligned, K even).
+// One lower tile t (linear index over the lower triangle of tiles) of one
+// K split; the whole workgroup takes part.
 template <int R, int Q, int KC, bool SCALE, bool VEC>
-__global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* __restrict__ X,
-                                                  long ldx, const double* __restrict__ w,
-                                                  double* __restrict__ C, long ldc, int sub,
-                                                  int ntiles, int per_xcd, int kchunk,
-                                                  double* __restrict__ part) {
+__device__ __forceinline__ void syrk_f64_tile(int mm, int K, const double* __restrict__ X,
+                                              long ldx, const double* __restrict__ w,
+                                              double* __restrict__ C, long ldc, int sub, int t,
+                                              int ntiles, int split, int kchunk,
+                                              double* __restrict__ part) {
   constexpr int BM = 8 * R;
   static_assert(BM == 32 * Q, "square tiles");
   constexpr int PPR = KC / 2;               // element pairs per row per stage
   constexpr int PAIRS = BM * PPR / 256;     // pairs per thread per operand
   __shared__ double lds[2][2][BM * KC];     // [stage][operand: 0 rows, 1 cols]
 
-  // XCD-aware order: consecutive tiles (sharing row panels) on one XCD.
-  const int b = blockIdx.x;
-  const int t = (b & 7) * per_xcd + (b >> 3);
-  if (t >= ntiles) return;
   int ti, tj;
   tile_coords(t, ti, tj);
   const int row0 = ti * BM, col0 = tj * BM;
-  const int split = blockIdx.y;
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
   const int nst = (kend - kbeg + KC - 1) / KC;
@@ -188,6 +185,20 @@ __global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* _
         *cp = sub ? (*cp - acc[r][q]) : acc[r][q];
       }
     }
+}
+
+template <int R, int Q, int KC, bool SCALE, bool VEC>
+__global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* __restrict__ X,
+                                                  long ldx, const double* __restrict__ w,
+                                                  double* __restrict__ C, long ldc, int sub,
+                                                  int ntiles, int per_xcd, int kchunk,
+                                                  double* __restrict__ part) {
+  // XCD-aware order: consecutive tiles (sharing row panels) on one XCD.
+  const int b = blockIdx.x;
+  const int t = (b & 7) * per_xcd + (b >> 3);
+  if (t >= ntiles) return;
+  syrk_f64_tile<R, Q, KC, SCALE, VEC>(mm, K, X, ldx, w, C, ldc, sub, t, ntiles, blockIdx.y,
+                                      kchunk, part);
 }
 
 // Ordered sum of split-K partial tiles into C (lower part only).
@@ -369,6 +380,41 @@ __global__ __launch_bounds__(256) void k_syrk_reduce_f32(int mm, float* __restri
 constexpr int kKC128 = 32;  // K per stage of the 128 x 128 tile kernel
 constexpr int kKC64 = 32;   // and of the 64 x 64 one
 
+// Batched normal matrices: LP = blockIdx.y, lower 64-tile blockIdx.x of
+// M_i = A_i diag(d_i) A_i^T (rows of A_i need not be 16-byte aligned).
+__global__ __launch_bounds__(256) void k_bsyrk_normal(const BatchLP* __restrict__ lps,
+                                                       const int* __restrict__ go,
+                                                       const double* __restrict__ A,
+                                                       const double* __restrict__ d,
+                                                       double* __restrict__ Mpool) {
+  const int lp = blockIdx.y;
+  if (!go[lp]) return;
+  const BatchLP P = lps[lp];
+  const int nt = (P.m + 63) / 64, ntiles = nt * (nt + 1) / 2;
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
+  syrk_f64_tile<8, 2, 32, true, false>(P.m, P.n, A + P.a_off, P.n, d + P.vn, Mpool + P.M_off,
+                                       P.ldm, 0, t, ntiles, 0, P.n, nullptr);
+}
+
+// Batched Cholesky trailing update after the panel at column p:
+// M22 -= L21 L21^T on the lower 64-tiles of each LP that has rows below p + 64.
+__global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restrict__ lps,
+                                                         const int* __restrict__ go,
+                                                         double* __restrict__ Mpool, int p) {
+  const int lp = blockIdx.y;
+  if (!go[lp]) return;
+  const BatchLP P = lps[lp];
+  const int mm = P.m - p - 64;
+  if (mm <= 0) return;
+  const int nt = (mm + 63) / 64, ntiles = nt * (nt + 1) / 2;
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
+  double* X = Mpool + P.M_off + (long)(p + 64) * P.ldm + p;
+  syrk_f64_tile<8, 2, 32, false, true>(mm, 64, X, P.ldm, nullptr, X + 64, P.ldm, 1, t, ntiles, 0,
+                                       64, nullptr);
+}
+
 }  // namespace
 
 size_t syrk_part_elems(int mm, int tile, int splits) {
@@ -483,6 +529,22 @@ bool launch_syrk_f32(hipStream_t st, int mm, int K, const float* X, long ldx, co
     hipLaunchKernelGGL(k_syrk_reduce_f32<BM>, dim3(ntiles), dim3(256), 0, st, mm, C, ldc,
                        (int)sub, ntiles, splits, part);
   return true;
+}
+
+void launch_bsyrk_normal(hipStream_t st, int count, int max_m, const BatchLP* lps, const int* go,
+                         const double* A, const double* d, double* Mpool) {
+  const int nt = cdiv(max_m, 64);
+  hipLaunchKernelGGL(k_bsyrk_normal, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st, lps, go, A,
+                     d, Mpool);
+}
+
+void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, const BatchLP* lps,
+                           const int* go, double* Mpool, int p) {
+  const int mm = max_m - p - 64;
+  if (mm <= 0) return;
+  const int nt = cdiv(mm, 64);
+  hipLaunchKernelGGL(k_bsyrk_trailing, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st, lps, go,
+                     Mpool, p);
 }
 
 }  // namespace pdas

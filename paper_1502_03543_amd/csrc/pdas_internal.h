@@ -103,10 +103,11 @@ size_t syrk_part_elems_f32(int mm, int splits);
 void syrk_choose_f32(int mm, int K, int* splits);
 
 // --- Cholesky (kernels_chol.hip) -------------------------------------------
-// In-place lower Cholesky of M (row-major, ld), m x m; failures recorded in info.
-void launch_potrf_f64(hipStream_t st, int m, double* M, long ld, DevInfo* info, double* part,
-                      size_t part_elems);
-void launch_potrf_f32(hipStream_t st, int m, float* M, long ld, DevInfo* info);
+// In-place lower Cholesky of M (row-major, ld), m x m; failures recorded in
+// info.  diag: scratch for the diagonal blocks, potrf_diag_elems(m) elements.
+inline long potrf_diag_elems(long m) { return (long)cdiv(m, kTB) * kTB * kTB; }
+void launch_potrf_f64(hipStream_t st, int m, double* M, long ld, DevInfo* info, double* diag);
+void launch_potrf_f32(hipStream_t st, int m, float* M, long ld, DevInfo* info, float* diag);
 
 // --- triangular solves (kernels_trsv.hip) ----------------------------------
 // z = L^-1 r (fwd) then y = L^-T z (bwd); L row-major lower with ld.
@@ -139,6 +140,7 @@ struct BatchLP {
   long vm, vn;    // element offsets of the m- and n-vectors of LP i
   long M_off;     // element offset of M_i (ldm x m) in the matrix pool
   long tape_off;  // element offset of LP i's tape
+  long diag_off;  // element offset of LP i's diagonal-block scratch
 };
 
 struct BatchState {
@@ -156,7 +158,6 @@ struct BatchArgs {
   int max_iter;
   double alpha, tol;
   const BatchLP* lps;
-  const int* order;     // processing order (largest m^2 n first)
   BatchState* state;
   const double* A;      // caller's packed matrices (offsets a_off)
   const double* b;      // workspace copies, packed by vm / vn
@@ -166,10 +167,15 @@ struct BatchArgs {
   double* s[2];
   double* rd[2];
   double *d, *w, *g, *gy, *dx, *ds, *rhs, *z, *dy, *M;
+  double* diag;         // diagonal blocks of the factors (potrf_diag_elems(m) per LP)
   double* tape;
   int tape_cap;
-  int* queue;
-  int* active;
+  int* active;          // LPs still iterating after the last step
+  int* go;              // per LP: 1 when it takes (or reverses) a step in this launch sequence
+  int* fail;            // per LP: first failing Cholesky pivot column, INT_MAX for none
+  unsigned long long* minp;  // per LP: smallest pivot (bit pattern of a positive double)
+  double* psi;          // per LP: psi of the current direction
+  long long* arg;       // per LP: its first maximiser (x block j, s block n + j)
 };
 
 // Adjoint pools of a batch (packed like the forward vectors; Abar like A).
@@ -179,12 +185,23 @@ struct BatchAdj {
   int* err;
 };
 
-__global__ void k_batch_iter(BatchArgs a);
-void launch_batch_iter(hipStream_t st, const BatchArgs& args, int grid);
-void launch_batch_backward(hipStream_t st, const BatchArgs& args, const BatchAdj& adj, int k,
-                           int grid);
+// One forward iteration of every active LP (k < 0), or the recomputation
+// and reverse of step k (k >= 0, with adj), as a fixed sequence of launches
+// whose shapes depend only on count and max_m (so it can be captured once).
+void launch_batch_step(hipStream_t st, const BatchArgs& args, int max_m, int k,
+                       const BatchAdj* adj);
 void launch_batch_setup(hipStream_t st, int count, const BatchLP* lps, BatchState* state,
                         const double* Ap, const double* c, const double* x, const double* y,
                         const double* s, double* rd);
+// batched building blocks (kernels_syrk.hip, kernels_chol.hip)
+void launch_bsyrk_normal(hipStream_t st, int count, int max_m, const BatchLP* lps, const int* go,
+                         const double* A, const double* d, double* Mpool);
+void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, const BatchLP* lps,
+                           const int* go, double* Mpool, int p);
+void launch_bpotrf_panel(hipStream_t st, int count, int max_m, const BatchLP* lps, const int* go,
+                         double* Mpool, double* diagpool, int p, int* fail,
+                         unsigned long long* minp_bits);
+void launch_bdiag_to_m(hipStream_t st, int count, int max_m, const BatchLP* lps, const int* go,
+                       double* Mpool, const double* diagpool);
 
 }  // namespace pdas

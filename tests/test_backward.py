@@ -93,7 +93,9 @@ def test_batch_backward_differentiable_config(torch_dev):
     lps = [lpgen.gen_lp(256, 1024, i) for i in range(64)]
     ws = [lpgen.loss_weights(1024, i) for i in range(64)]
     bt = solver.Batch(lps, alpha=0.9, tape_capacity=K)
+    print("64 LPs set up, forward", flush=True)
     res = bt.solve(0.0, K)
+    print("forward done, reverse", flush=True)
     assert all(capi.status_string(s) == "LP_MAX_ITER" for s in res["status"]), res["status"]
     assert all(it == K for it in res["iters"])
     g = bt.backward(torch.from_numpy(np.concatenate(ws)).to(dev))

@@ -1,5 +1,6 @@
-"""Batched solver (one launch per iteration for all LPs) against the oracle,
-LP by LP, on ragged shapes m ~ U{16..256}, n = round(r m), r ~ U(3, 5)."""
+"""Batched solver (one captured launch sequence per iteration for all LPs)
+against the oracle, LP by LP, on ragged shapes m ~ U{16..256}, n = round(r m),
+r ~ U(3, 5)."""
 import numpy as np
 import pytest
 
@@ -36,7 +37,9 @@ def test_batch_small_matches_oracle(torch_dev):
     lps = lpgen.gen_batch(24, first_seed=100)
     print("shapes:", [lp.A.shape for lp in lps], flush=True)
     bt = solver.Batch(lps, alpha=0.95)
+    print("batch set up, solving", flush=True)
     res = bt.solve(1e-8, 200)
+    print("solved:", list(res["iters"]), flush=True)
     its = bt.iterates()
     for i, lp in enumerate(lps):
         _oracle_check(lp, res["status"][i], res["iters"][i], *its[i])
@@ -85,6 +88,7 @@ def test_batch_512_ragged(torch_dev):
     from paper_1502_03543_amd import solver
     lps = lpgen.gen_batch(512, first_seed=0)
     bt = solver.Batch(lps, alpha=0.95)
+    print("512 LPs set up, solving", flush=True)
     res = bt.solve(1e-8, 200)
     its = bt.iterates()
     names = [capi.status_string(s) for s in res["status"]]
