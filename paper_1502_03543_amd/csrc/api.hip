@@ -123,8 +123,8 @@ void carve(lp_handle* h, Carver& cv) {
   h->ds = cv.take<double>(n);
   h->g = cv.take<double>(n);
   h->gy = cv.take<double>(n);
-  h->ldm = (m + 7) / 8 * 8;
-  h->M = cv.take<double>((size_t)h->ldm * m);
+  h->ldm = (m + 1 + 7) / 8 * 8;  // a column beyond m: the right-hand-side row reaches (m, m)
+  h->M = cv.take<double>((size_t)h->ldm * (m + 1));  // row m: the right-hand side
   h->diag = cv.take<double>(potrf_diag_elems(m));
   syrk_choose((int)m, (int)n, &h->syrk_tile, &h->syrk_splits);
   h->syrk_part_n = syrk_part_elems((int)m, h->syrk_tile, h->syrk_splits);
@@ -354,10 +354,12 @@ static void solve_fp64(lp_handle* h) {
                   h->profiling ? h->ev[lp_handle::EV_SYRKK0] : nullptr,
                   h->profiling ? h->ev[lp_handle::EV_SYRKK1] : nullptr);
   mark(h, lp_handle::EV_SYRK1);
-  launch_potrf_f64(s, (int)m, h->M, h->ldm, h->info, h->diag);
+  // rhs rides along as row m of the factorization: it leaves as z = L^-1 rhs
+  double* zrow = h->M + (size_t)m * h->ldm;
+  launch_copy(s, zrow, h->rhs, m);
+  launch_potrf_f64(s, (int)m + 1, (int)m, h->M, h->ldm, h->info, h->diag);
   mark(h, lp_handle::EV_CHOL1);
-  launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
-  launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
+  launch_trsv_bwd(s, (int)m, h->M, h->ldm, zrow, h->dy, h->trsv_sync, h->info);
   h->last_prec = LP_PREC_FP64;
 }
 
@@ -624,9 +626,10 @@ lp_status lp_backward(lp_handle* h, const double* xbar_K, const double* ybar_K,
     launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
     launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->d, h->M, h->ldm, false, h->syrk_tile,
                     h->syrk_splits, h->syrk_part);
-    launch_potrf_f64(s, (int)m, h->M, h->ldm, h->info, h->diag);
-    launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
-    launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
+    double* zrow = h->M + (size_t)m * h->ldm;
+    launch_copy(s, zrow, h->rhs, m);
+    launch_potrf_f64(s, (int)m + 1, (int)m, h->M, h->ldm, h->info, h->diag);
+    launch_trsv_bwd(s, (int)m, h->M, h->ldm, zrow, h->dy, h->trsv_sync, h->info);
     launch_gemv_t(s, m, n, h->A, h->dy, h->by, h->P1, h->P2);
     launch_dir(s, m, n, h->P1, h->P2, h->nchunks, h->brd, h->bx, h->bs, h->d, h->dx, h->ds,
                h->gy, h->g, h->rpart, h->ipart, h->zpart, h->npart);
@@ -758,7 +761,7 @@ lp_status lp_cholesky(int64_t m, double* M, int64_t ldm, void* workspace, size_t
   if (st != LP_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   launch_iter_begin(s, b.info, b.sync, cdiv(m, kTB));
-  launch_potrf_f64(s, (int)m, M, ldm, b.info, b.diag);
+  launch_potrf_f64(s, (int)m, (int)m, M, ldm, b.info, b.diag);
   DevInfo di;
   hipError_t e = hipMemcpyAsync(&di, b.info, sizeof(di), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -14,6 +14,9 @@
 //      L21 = M21 L11^-T by forward substitution.  Workgroup 0 stores L11.
 //   2. trailing update M22 -= L21 L21^T on the matrix cores (the normal-matrix
 //      kernel in subtract mode, lower tiles only).
+// Rows below the last column (mr > mc) are carried through both steps like
+// any other row: a right-hand side stored as row m comes out as (L^-1 r)^T,
+// so the forward triangular solve costs no launch of its own.
 // The pivot reciprocal square root is the hardware estimate refined by Newton
 // steps (within an ulp or two of the correctly rounded value).  A pivot that
 // is not a finite positive number is recorded (first column) in the
@@ -161,24 +164,26 @@ __device__ __forceinline__ void solve_steps(std::integer_sequence<int, Cs...>, T
   (solve_step<T, Cs>(x, ltz, dz), ...);
 }
 
-// Workgroup wg of the panel step at column p: every workgroup factors A11
+// Workgroup wg of the panel step at column p of an mr x mc lower matrix
+// (mr >= mc; rows beyond mc are extra right-hand sides stored as rows, whose
+// factor rows come out as L^-1 applied to them): every workgroup factors A11
 // from M; wg 0 stores L11 into diag_blk (64 x 64 row-major, lower part) and
 // reports the first failing pivot column and the smallest pivot; wg >= 1 also
-// solve rows p + 64 + 192 (wg - 1) ... of L21 in place.  L11 goes to the side
-// block, not to M, because other workgroups of the same launch may still be
-// reading A11 from M; the blocks are copied into M after the last panel.
+// solve rows p + nbe + 192 (wg - 1) ... of L21 in place.  L11 goes to the
+// side block, not to M, because other workgroups of the same launch may still
+// be reading A11 from M; the blocks are copied into M after the last panel.
 template <typename T>
-__device__ __forceinline__ void potrf_panel_body(int m, T* __restrict__ M, long ld, int p, int wg,
-                                                 T* __restrict__ diag_blk, int* fail_out,
+__device__ __forceinline__ void potrf_panel_body(int mr, int mc, T* __restrict__ M, long ld, int p,
+                                                 int wg, T* __restrict__ diag_blk, int* fail_out,
                                                  unsigned long long* minp_bits_out) {
   __shared__ T col[2][NB];             // column j of L11 (lane i writes row i)
   __shared__ T lt[NB][NB + 1];         // A11 on entry; L11 transposed on exit: lt[c][k] = L[k][c]
   __shared__ T dinv[NB];
   __shared__ T S[kRowsPerWG][NB + 1];  // staged panel rows of this workgroup
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nbe = min(NB, m - p);
+  const int nbe = min(NB, mc - p);
   const bool solve = wg > 0;
-  const long r0 = (long)p + NB + (long)(wg - 1) * kRowsPerWG;
+  const long r0 = (long)p + nbe + (long)(wg - 1) * kRowsPerWG;
 
   // stage A11 (identity beyond the matrix; upper part never read) and the
   // workgroup's panel rows, coalesced
@@ -188,12 +193,14 @@ __device__ __forceinline__ void potrf_panel_body(int m, T* __restrict__ M, long 
     lt[r][k] = (r < nbe && k < nbe) ? v : ((r == k) ? T(1) : T(0));
   }
   if (solve) {
+    // columns clamped to the panel (nbe < 64 only in the last panel, whose
+    // rows below are extra right-hand-side rows)
     for (int e = tid; e < kRowsPerWG * (NB / 2); e += 256) {
       const int row = e / (NB / 2), kp = 2 * (e % (NB / 2));
-      const long gr = min(r0 + row, (long)m - 1);
-      const T* src = M + gr * ld + p + kp;
-      S[row][kp] = src[0];
-      S[row][kp + 1] = src[1];
+      const long gr = min(r0 + row, (long)mr - 1);
+      const T* src = M + gr * ld + p;
+      S[row][kp] = src[min(kp, nbe - 1)];
+      S[row][kp + 1] = src[min(kp + 1, nbe - 1)];
     }
   }
   __syncthreads();
@@ -240,17 +247,19 @@ __device__ __forceinline__ void potrf_panel_body(int m, T* __restrict__ M, long 
   for (int k = 0; k < NB; ++k) x[k] = S[row][k];
   const int z1 = opaque_zero();
   solve_steps<T>(std::make_integer_sequence<int, NB>{}, x, &lt[0][0] + z1, dinv + z1);
-  if (rr < m) {
+  if (rr < mr) {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) M[rr * ld + p + k] = x[k];
+    for (int k = 0; k < NB; ++k)
+      if (k < nbe) M[rr * ld + p + k] = x[k];
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_panel(int m, T* __restrict__ M, long ld, int p,
-                                                      T* __restrict__ diag, DevInfo* info) {
-  potrf_panel_body<T>(m, M, ld, p, blockIdx.x, diag + (long)(p / NB) * NB * NB, &info->chol_fail,
-                      reinterpret_cast<unsigned long long*>(&info->min_pivot));
+__global__ __launch_bounds__(256) void k_potrf_panel(int mr, int mc, T* __restrict__ M, long ld,
+                                                      int p, T* __restrict__ diag,
+                                                      DevInfo* info) {
+  potrf_panel_body<T>(mr, mc, M, ld, p, blockIdx.x, diag + (long)(p / NB) * NB * NB,
+                      &info->chol_fail, reinterpret_cast<unsigned long long*>(&info->min_pivot));
 }
 
 // Diagonal blocks from the side buffer into M (lower parts); one workgroup
@@ -283,7 +292,7 @@ __global__ __launch_bounds__(256) void k_bpotrf_panel(const BatchLP* __restrict_
   if (!go[lp] || p >= P.m) return;
   const int below = P.m - p - min(NB, P.m - p);
   if ((int)blockIdx.x > (below + kRowsPerWG - 1) / kRowsPerWG) return;
-  potrf_panel_body<double>(P.m, Mpool + P.M_off, P.ldm, p, blockIdx.x,
+  potrf_panel_body<double>(P.m, P.m, Mpool + P.M_off, P.ldm, p, blockIdx.x,
                            diagpool + P.diag_off + (long)(p / NB) * NB * NB, fail + lp,
                            minp_bits + lp);
 }
@@ -300,19 +309,19 @@ __global__ __launch_bounds__(256) void k_bdiag_to_m(const BatchLP* __restrict__ 
 
 }  // namespace
 
-void launch_potrf_f64(hipStream_t st, int m, double* M, long ld, DevInfo* info, double* diag) {
-  for (int p = 0; p < m; p += NB) {
-    const int nbe = (m - p) < NB ? (m - p) : NB;
-    const int below = m - p - nbe;
-    const int grid = 1 + cdiv(below, kRowsPerWG);
-    hipLaunchKernelGGL(k_potrf_panel<double>, dim3(grid), dim3(256), 0, st, m, M, ld, p, diag,
-                       info);
-    if (below > 0) {
-      launch_syrk_f64(st, below, NB, M + (long)(p + NB) * ld + p, ld, nullptr,
+void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInfo* info,
+                      double* diag) {
+  for (int p = 0; p < mc; p += NB) {
+    const int nbe = (mc - p) < NB ? (mc - p) : NB;
+    const int grid = 1 + cdiv(mr - p - nbe, kRowsPerWG);
+    hipLaunchKernelGGL(k_potrf_panel<double>, dim3(grid), dim3(256), 0, st, mr, mc, M, ld, p,
+                       diag, info);
+    if (p + NB < mc) {
+      launch_syrk_f64(st, mr - p - NB, NB, M + (long)(p + NB) * ld + p, ld, nullptr,
                       M + (long)(p + NB) * ld + (p + NB), ld, true, 64, 1, nullptr);
     }
   }
-  hipLaunchKernelGGL(k_diag_to_m<double>, dim3(cdiv(m, NB)), dim3(256), 0, st, m, M, ld, diag);
+  hipLaunchKernelGGL(k_diag_to_m<double>, dim3(cdiv(mc, NB)), dim3(256), 0, st, mc, M, ld, diag);
 }
 
 void launch_potrf_f32(hipStream_t st, int m, float* M, long ld, DevInfo* info, float* diag) {
@@ -320,7 +329,7 @@ void launch_potrf_f32(hipStream_t st, int m, float* M, long ld, DevInfo* info, f
     const int nbe = (m - p) < NB ? (m - p) : NB;
     const int below = m - p - nbe;
     const int grid = 1 + cdiv(below, kRowsPerWG);
-    hipLaunchKernelGGL(k_potrf_panel<float>, dim3(grid), dim3(256), 0, st, m, M, ld, p, diag,
+    hipLaunchKernelGGL(k_potrf_panel<float>, dim3(grid), dim3(256), 0, st, m, m, M, ld, p, diag,
                        info);
     if (below > 0)
       launch_syrk_f32(st, below, NB, M + (long)(p + NB) * ld + p, ld, nullptr,

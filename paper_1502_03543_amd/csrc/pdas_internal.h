@@ -105,8 +105,13 @@ void syrk_choose_f32(int mm, int K, int* splits);
 // --- Cholesky (kernels_chol.hip) -------------------------------------------
 // In-place lower Cholesky of M (row-major, ld), m x m; failures recorded in
 // info.  diag: scratch for the diagonal blocks, potrf_diag_elems(m) elements.
+// The FP64 form factors the first mc columns of an mr-row lower matrix
+// (mr >= mc): rows mc .. mr-1 leave as L^-1 applied to them (forward solves
+// fused into the factorization).  With mr > mc the trailing updates also
+// write the entries (r, c) of those rows for c <= r, so ld must exceed mr - 1.
 inline long potrf_diag_elems(long m) { return (long)cdiv(m, kTB) * kTB * kTB; }
-void launch_potrf_f64(hipStream_t st, int m, double* M, long ld, DevInfo* info, double* diag);
+void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInfo* info,
+                      double* diag);
 void launch_potrf_f32(hipStream_t st, int m, float* M, long ld, DevInfo* info, float* diag);
 
 // --- triangular solves (kernels_trsv.hip) ----------------------------------
