@@ -1,0 +1,78 @@
+"""Build the CPU emulation of the library's kernels (test infrastructure only).
+
+The HIP sources are compiled unchanged for the host with tests/emu/hip as the
+runtime, except for two textual substitutions: the one inline-asm register
+move (a compiler-opaque zero) becomes a plain zero, and the workspace carver
+of the batched solver gains poisoned guard zones between its pools, so that
+AddressSanitizer reports any kernel access that leaves its own pool.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_1502_03543_amd", "csrc")
+BUILD = os.path.join(HERE, "_build")
+SOURCES = ["kernels_batch", "api_batch", "kernels_chol", "kernels_syrk"]
+
+ASM_ZERO = 'asm volatile("v_mov_b32 %0, 0" : "=v"(z));'
+CARVE_OLD = """    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;"""
+CARVE_NEW = """    off = (off + kAlign - 1) / kAlign * kAlign;
+    off += 512;
+    if (base) __asan_poison_memory_region(base + off - 512, 512);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;"""
+
+
+def compiler() -> str | None:
+    for c in ("/opt/rocm/llvm/bin/clang++", shutil.which("clang++")):
+        if c and os.path.exists(c):
+            return c
+    return None
+
+
+def build() -> str:
+    cxx = compiler()
+    if cxx is None:
+        raise RuntimeError("no clang++ for the kernel emulation")
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    flags = ["-O1", "-g", "-std=c++20", "-fsanitize=address", "-fno-omit-frame-pointer",
+             "-I" + HERE, "-I" + CSRC, "-I" + os.path.join(ROOT, "include"),
+             "-include", os.path.join(HERE, "hip", "hip_runtime.h")]
+    jobs = []
+    for name in SOURCES:
+        text = open(os.path.join(CSRC, name + ".hip")).read()
+        if name == "kernels_chol":
+            if ASM_ZERO not in text:
+                raise RuntimeError("kernels_chol.hip: opaque-zero asm not found")
+            text = text.replace(ASM_ZERO, "z = 0;")
+        if name == "api_batch":
+            if CARVE_OLD not in text:
+                raise RuntimeError("api_batch.hip: workspace carver not found")
+            text = "#include <sanitizer/asan_interface.h>\n" + text.replace(CARVE_OLD, CARVE_NEW)
+        cpp = os.path.join(BUILD, name + ".cpp")
+        with open(cpp, "w") as f:
+            f.write(text)
+        jobs.append(cpp)
+    jobs += [os.path.join(HERE, "emu_runtime.cpp"), os.path.join(HERE, "drivers.cpp")]
+    procs = []
+    for src in jobs:
+        obj = os.path.join(BUILD, os.path.basename(src).replace(".cpp", ".o"))
+        procs.append(subprocess.Popen([cxx, *flags, "-c", src, "-o", obj],
+                                      stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
+        objs.append(obj)
+    for p, src in zip(procs, jobs):
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"emulation build failed for {src}:\n{out.decode()[-3000:]}")
+    exe = os.path.join(BUILD, "emu")
+    subprocess.run([cxx, "-fsanitize=address", "-o", exe, *objs], check=True)
+    return exe
+
+
+if __name__ == "__main__":
+    print(build())

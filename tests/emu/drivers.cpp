@@ -1,0 +1,157 @@
+// Host drivers for the emulated kernels (test infrastructure only).
+//   emu chol <m>                      lower Cholesky of a fixed SPD matrix with
+//                                     one extra right-hand-side row; prints
+//                                     the factor and forward-solve errors
+//                                     against a long-double reference
+//   emu batch <in> <out> <max_iter> <tape>
+//                                     batched solve of the LPs in <in>; with a
+//                                     tape, also the reverse sweep
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hip/hip_runtime.h"
+#include "pdas_internal.h"
+
+namespace pdas {
+void launch_fill_i32(hipStream_t, int* p, int v, long count) {
+  for (long i = 0; i < count; ++i) p[i] = v;
+}
+void launch_copy(hipStream_t, double* d, const double* s, long n) {
+  std::memcpy(d, s, n * sizeof(double));
+}
+void launch_zero(hipStream_t, double* p, long n) {
+  for (long i = 0; i < n; ++i) p[i] = 0.0;
+}
+}  // namespace pdas
+
+extern "C" void lp_options_default(lp_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->alpha = 0.95;
+  o->precision = LP_PREC_FP64;
+  o->mixed_switch_gap = 1e-6;
+  o->refine_tol = 0x1p-46;
+  o->refine_max = 5;
+}
+
+static int run_chol(int m) {
+  const long ld = (m + 1 + 7) / 8 * 8;
+  std::vector<double> A((size_t)(m + 1) * ld, NAN);  // upper part never read
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j <= i; ++j)
+      A[(size_t)i * ld + j] = (i == j) ? m : 0.5 / (1.0 + std::abs(i - j)) + 0.01 * ((i * 7 + j * 3) % 11);
+  for (int j = 0; j < m; ++j) A[(size_t)m * ld + j] = std::cos(0.3 * j);
+  std::vector<double> M = A, diag(pdas::potrf_diag_elems(m));
+  pdas::DevInfo info{};
+  info.chol_fail = INT_MAX;
+  info.min_pivot = INFINITY;
+  pdas::launch_potrf_f64(nullptr, m + 1, m, M.data(), ld, &info, diag.data());
+  std::vector<long double> R((size_t)m * m, 0.0L);
+  for (int j = 0; j < m; ++j)
+    for (int i = j; i < m; ++i) {
+      long double s = A[(size_t)i * ld + j];
+      for (int k = 0; k < j; ++k) s -= R[(size_t)i * m + k] * R[(size_t)j * m + k];
+      R[(size_t)i * m + j] = (i == j) ? sqrtl(s) : s / R[(size_t)j * m + j];
+    }
+  double lerr = 0, lsc = 0, zerr = 0, zsc = 0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j <= i; ++j) {
+      lerr = std::fmax(lerr, std::fabs((double)(M[(size_t)i * ld + j] - R[(size_t)i * m + j])));
+      lsc = std::fmax(lsc, std::fabs((double)R[(size_t)i * m + j]));
+    }
+  std::vector<long double> z(m);
+  for (int i = 0; i < m; ++i) {
+    long double v = A[(size_t)m * ld + i];
+    for (int k = 0; k < i; ++k) v -= R[(size_t)i * m + k] * z[k];
+    z[i] = v / R[(size_t)i * m + i];
+    zerr = std::fmax(zerr, std::fabs((double)(z[i] - M[(size_t)m * ld + i])));
+    zsc = std::fmax(zsc, std::fabs((double)z[i]));
+  }
+  printf("{\"m\": %d, \"fail\": %d, \"factor_rel_err\": %.3e, \"solve_rel_err\": %.3e}\n", m,
+         info.chol_fail == INT_MAX ? -1 : info.chol_fail, lerr / lsc, zerr / zsc);
+  return 0;
+}
+
+static int run_batch(const char* in, const char* out, int max_iter, int tape) {
+  FILE* f = fopen(in, "rb");
+  if (!f) return 2;
+  int count = 0;
+  if (fread(&count, 4, 1, f) != 1) return 2;
+  std::vector<int64_t> m(count), n(count), aoff(count), vom(count), von(count);
+  std::vector<double> A, b, c, x0, y0, s0;
+  for (int i = 0; i < count; ++i) {
+    int64_t mn[2];
+    if (fread(mn, 8, 2, f) != 2) return 2;
+    m[i] = mn[0];
+    n[i] = mn[1];
+    aoff[i] = A.size();
+    vom[i] = b.size();
+    von[i] = c.size();
+    auto rd = [&](std::vector<double>& v, long k) {
+      const size_t o = v.size();
+      v.resize(o + k);
+      return fread(v.data() + o, 8, k, f) == (size_t)k;
+    };
+    if (!(rd(A, m[i] * n[i]) && rd(b, m[i]) && rd(c, n[i]) && rd(x0, n[i]) && rd(y0, m[i]) &&
+          rd(s0, n[i])))
+      return 2;
+  }
+  fclose(f);
+  lp_options opt;
+  lp_options_default(&opt);
+  opt.tape_capacity = tape;
+  size_t bytes = 0;
+  int st = lp_batch_workspace_size(count, m.data(), n.data(), &opt, &bytes);
+  if (st != LP_OK) return 3;
+  void* ws = aligned_alloc(256, (bytes + 255) / 256 * 256);
+  std::memset(ws, 0xff, bytes);  // NaN patterns, as an uninitialised pool might hold
+  lp_batch* h = nullptr;
+  st = lp_batch_setup(&h, count, m.data(), n.data(), A.data(), aoff.data(), b.data(), c.data(),
+                      x0.data(), y0.data(), s0.data(), vom.data(), von.data(), &opt, ws, bytes,
+                      nullptr);
+  if (st != LP_OK) return 4;
+  std::vector<int32_t> status(count), iters(count);
+  int nconv = 0;
+  st = lp_batch_solve(h, tape > 0 ? 0.0 : 1e-8, max_iter, status.data(), iters.data(), &nconv);
+  if (st != LP_OK) return 5;
+  std::vector<double> x(c.size()), y(b.size()), s(c.size());
+  lp_batch_get_iterate(h, x.data(), y.data(), s.data());
+  FILE* o = fopen(out, "wb");
+  fwrite(status.data(), 4, count, o);
+  fwrite(iters.data(), 4, count, o);
+  fwrite(x.data(), 8, x.size(), o);
+  fwrite(y.data(), 8, y.size(), o);
+  fwrite(s.data(), 8, s.size(), o);
+  if (tape > 0) {
+    std::vector<double> xb(c.size()), Ab(A.size()), bb(b.size()), cb(c.size());
+    for (size_t j = 0; j < xb.size(); ++j) xb[j] = std::sin(0.37 * j + 0.1);
+    st = lp_batch_backward(h, xb.data(), nullptr, nullptr, Ab.data(), bb.data(), cb.data(),
+                           nullptr, nullptr, nullptr);
+    if (st != LP_OK) return 6;
+    fwrite(Ab.data(), 8, Ab.size(), o);
+    fwrite(bb.data(), 8, bb.size(), o);
+    fwrite(cb.data(), 8, cb.size(), o);
+    for (int k = 0; k < tape; ++k) {
+      std::vector<double> tx(c.size()), ty(b.size()), ts(c.size());
+      lp_batch_tape_row(h, k, tx.data(), ty.data(), ts.data());
+      fwrite(tx.data(), 8, tx.size(), o);
+      fwrite(ty.data(), 8, ty.size(), o);
+      fwrite(ts.data(), 8, ts.size(), o);
+    }
+  }
+  fclose(o);
+  lp_batch_destroy(h);
+  free(ws);
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  if (argc >= 3 && !strcmp(argv[1], "chol")) return run_chol(atoi(argv[2]));
+  if (argc >= 6 && !strcmp(argv[1], "batch"))
+    return run_batch(argv[2], argv[3], atoi(argv[4]), atoi(argv[5]));
+  fprintf(stderr, "usage: emu chol <m> | emu batch <in> <out> <max_iter> <tape>\n");
+  return 1;
+}

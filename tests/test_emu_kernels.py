@@ -1,0 +1,118 @@
+"""Kernel logic on the CPU: the HIP sources of the Cholesky (panel routine,
+trailing update, forward solve fused as an extra row) and of the batched
+solver (forward and reverse sweeps) run under the host emulation of
+tests/emu (workgroups as fibers, wavefront lock-step, AddressSanitizer), and
+are checked against a long-double reference and against the oracle.
+
+These tests run without a GPU; they check indexing, synchronisation and the
+algorithm, not the hardware's rounding (the emulated matrix-core and
+reciprocal-square-root instructions are exact-rounded host operations)."""
+import importlib.util
+import json
+import os
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1502_03543_amd import lpgen
+
+_spec = importlib.util.spec_from_file_location(
+    "build_emu", os.path.join(os.path.dirname(os.path.abspath(__file__)), "emu", "build_emu.py"))
+build_emu = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(build_emu)
+
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:detect_stack_use_after_return=0")
+
+
+@pytest.fixture(scope="module")
+def emu():
+    if build_emu.compiler() is None:
+        pytest.skip("no clang++ for the kernel emulation")
+    return build_emu.build()
+
+
+def _run(exe, *args, timeout=600):
+    p = subprocess.run([exe, *map(str, args)], capture_output=True, text=True, timeout=timeout,
+                       env=ENV)
+    assert p.returncode == 0, p.stdout[-2000:] + p.stderr[-4000:]
+    return p.stdout
+
+
+@pytest.mark.parametrize("m", [40, 64, 100, 150, 300])
+def test_emulated_cholesky_with_fused_forward_solve(emu, m):
+    r = json.loads(_run(emu, "chol", m).strip().splitlines()[-1])
+    assert r["fail"] == -1
+    assert r["factor_rel_err"] <= 1e-13, r
+    assert r["solve_rel_err"] <= 1e-13, r
+
+
+def _write(path, lps):
+    with open(path, "wb") as f:
+        f.write(struct.pack("i", len(lps)))
+        for lp in lps:
+            m, n = lp.A.shape
+            f.write(struct.pack("qq", m, n))
+            for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0):
+                f.write(np.ascontiguousarray(v, dtype=np.float64).tobytes())
+
+
+def _lps():
+    lps = [lpgen.gen_lp(40, 150, 3), lpgen.gen_lp(70, 260, 4), lpgen.gen_lp(33, 101, 5)]
+    bad = lpgen.gen_lp(30, 90, 6)
+    bad.A = bad.A.copy()
+    bad.A[3] = 0.0                      # zero row: exact zero pivot in this LP only
+    bad.b = bad.A @ bad.x0
+    return lps + [bad]
+
+
+def test_emulated_batch_matches_oracle(emu, tmp_path):
+    lps = _lps()
+    _write(tmp_path / "in.bin", lps)
+    _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0)
+    raw = (tmp_path / "out.bin").read_bytes()
+    k = len(lps)
+    st = np.frombuffer(raw[:4 * k], np.int32)
+    it = np.frombuffer(raw[4 * k:8 * k], np.int32)
+    sn = sum(lp.A.shape[1] for lp in lps)
+    y = np.frombuffer(raw[8 * k:], np.float64)[sn:]
+    names = {1: "CONVERGED", 2: "OPTIMAL_PSI1", -4: "ERR_BREAKDOWN"}
+    om = 0
+    for i, lp in enumerate(lps):
+        m = lp.A.shape[0]
+        ro = oracle.solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95, 1e-8, 200)
+        assert names.get(int(st[i])) == ro.status_name, (i, st[i], ro.status_name)
+        assert it[i] == ro.iters
+        if ro.status == oracle.CONVERGED:
+            byo = lp.b @ ro.y
+            assert abs(lp.b @ y[om:om + m] - byo) <= 1e-9 * max(1.0, abs(byo))
+        om += m
+
+
+def test_emulated_batch_reverse_matches_oracle(emu, tmp_path):
+    K = 3
+    lps = _lps()[:3]
+    _write(tmp_path / "in.bin", lps)
+    _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", K, K)
+    raw = np.frombuffer((tmp_path / "out.bin").read_bytes()[8 * len(lps):], np.float64)
+    ms = [lp.A.shape[0] for lp in lps]
+    ns = [lp.A.shape[1] for lp in lps]
+    sm, sn, sa = sum(ms), sum(ns), sum(a * b for a, b in zip(ms, ns))
+    g = raw[2 * sn + sm:]
+    Ab, bb, cb = g[:sa], g[sa:sa + sm], g[sa + sm:sa + sm + sn]
+    rows = g[sa + sm + sn:].reshape(K, 2 * sn + sm)
+    ao = vm = vn = 0
+    for lp, m, n in zip(lps, ms, ns):
+        tape = np.stack([np.concatenate([r[vn:vn + n], r[sn + vm:sn + vm + m],
+                                         r[sn + sm + vn:sn + sm + vn + n]]) for r in rows])
+        xb = np.sin(0.37 * np.arange(vn, vn + n) + 0.1)
+        st, go = oracle.backward(lp.A, lp.b, lp.c, 0.95, K, tape, xb)
+        assert st == oracle.CONTINUE
+        for got, ref in ((Ab[ao:ao + m * n].reshape(m, n), go["Abar"]),
+                         (bb[vm:vm + m], go["bbar"]), (cb[vn:vn + n], go["cbar"])):
+            assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+        ao += m * n
+        vm += m
+        vn += n
