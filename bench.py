@@ -11,7 +11,11 @@ Prints one JSON line: LP solves/s, plus the normal-matrix kernel's roofline
 (FP64 MFMA), the GFLOP/s of normal matrix + Cholesky, and the CPU oracle
 timed on a bounded sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+The same line carries the batched comparison (512 ragged LPs solved together
+against the single-LP FP64 solver applied LP by LP on a sample of them).
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants]
+  python bench.py --mixed-compare   # m=8192, n=32768: mixed precision vs FP64, one solve each
   python bench.py --copy-probe      # plain 256 MiB copies (counter scaling)
 """
 from __future__ import annotations
@@ -85,6 +89,89 @@ def cpu_baseline(lp, iters_gpu: int, sample_iters: int) -> dict:
     }
 
 
+def batch_variant(lpgen, solver, capi, torch, sample: int = 32) -> dict:
+    """512 ragged LPs (seeds 0..511) solved together vs. the single-LP FP64
+    solver applied LP by LP to the first `sample` of them."""
+    import numpy as np
+
+    lps = lpgen.gen_batch(512, first_seed=0)
+    warm = solver.Batch(lps, alpha=0.95)
+    warm.solve(1e-8, 200)
+    warm.close()
+    bt = solver.Batch(lps, alpha=0.95)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = bt.solve(1e-8, 200)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    names = [capi.status_string(int(v)) for v in res["status"]]
+    bt.close()
+    dev = torch.device("cuda:0")
+    hs = []
+    for lp in lps[:sample]:
+        T = [torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+             for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
+        hs.append((solver.LP(*T, alpha=0.95), T))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h, _ in hs:
+        h.solve(1e-8, 200)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for h, _ in hs:
+        h.close()
+    return {
+        "workload": "512 LPs, m ~ U{16..256}, n = round(r m), r ~ U(3,5), seeds 0..511, FP64, "
+                    "alpha 0.95, to gap 1e-8",
+        "batched_lps_per_s": len(lps) / tb,
+        "batched_ms": tb * 1e3,
+        "fp64_lp_by_lp_lps_per_s": sample / ts,
+        "lp_by_lp_sample": f"single-LP solver on LPs 0..{sample - 1}, one after another",
+        "speedup_vs_lp_by_lp": (len(lps) / tb) / (sample / ts),
+        "status_counts": {k: names.count(k) for k in sorted(set(names))},
+    }
+
+
+def mixed_compare():
+    """m=8192, n=32768: one mixed-precision solve and one FP64 solve from the
+    same start, with the per-iteration precision and refinement counts."""
+    import numpy as np
+    import torch
+
+    from paper_1502_03543_amd import capi, lpgen, solver
+
+    capi.load()
+    dev = torch.device("cuda:0")
+    lp = lpgen.gen_lp(8192, 32768, 0)
+    T = [torch.from_numpy(v).to(dev) for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
+    del lp
+    out = {"workload": "single LP m=8192 n=32768, Gaussian A, alpha 0.95, to gap 1e-8"}
+    for prec in ("mixed", "fp64"):
+        h = solver.LP(*T, alpha=0.95, precision=prec, profile=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = h.solve(1e-8, 300, want_log=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tim = h.timings()
+        log = r.get("log") or []
+        out[prec] = {
+            "status": capi.status_string(r["status"]), "iterations": r["iters"] + 1,
+            "seconds": dt, "dual_obj": r["dual_obj"],
+            "fp32_iterations": sum(1 for e in log if e["precision_used"] == capi.LP_PREC_MIXED),
+            "refine_steps": [e["refine_steps"] for e in log],
+            "ms_per_iteration": tim["iter_ms"] / max(tim["iterations"], 1),
+            "normal_ms_per_iteration": tim["normal_ms"] / max(tim["iterations"], 1),
+            "cholesky_ms_per_iteration": tim["potrf_ms"] / max(tim["iterations"], 1),
+        }
+        h.close()
+        print(json.dumps({prec: out[prec]}), flush=True)
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    out["dual_obj_rel_diff"] = abs(out["mixed"]["dual_obj"] - out["fp64"]["dual_obj"]) / max(
+        1.0, abs(out["fp64"]["dual_obj"]))
+    print(json.dumps(out))
+
+
 def copy_probe():
     import torch
 
@@ -108,6 +195,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--mixed-compare", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -116,6 +205,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.mixed_compare:
+        mixed_compare()
         return
 
     import numpy as np
@@ -204,10 +296,12 @@ def main():
             "avg_launch_ms": kernel_ms,
         },
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(lp, K, args.cpu_sample_iters)
     for h in handles:
         h.close()
+    if not args.no_variants:
+        out["variants"] = {"batched": batch_variant(lpgen, solver, capi, torch)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(lp, K, args.cpu_sample_iters)
     print(json.dumps(out))
 
 

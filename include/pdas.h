@@ -85,10 +85,17 @@ typedef struct lp_options {
                               back (default 5)                                   */
   int32_t profile;         /* non-zero: time each phase with HIP events on the
                               handle's stream (see lp_get_timings)               */
+  int32_t syrk_tile;       /* FP64 normal-matrix workgroup tile: 0 (library's
+                              choice), 64 or 128; see paper_1502_03543_amd/
+                              autotune.py for the measured choice               */
+  int32_t syrk_splits;     /* FP64 normal-matrix split of the sum over j:
+                              0 (library's choice) or 1..64                     */
+  int32_t syrk32_splits;   /* FP32 normal-matrix split (MIXED): 0 or 1..64      */
+  int32_t reserved;        /* must be 0                                          */
 } lp_options;
 
 /* Fill *opt with the defaults: alpha 0.95, FP64, no tape, switch gap 1e-6,
- * refine_tol 2^-46, refine_max 5, no profiling. */
+ * refine_tol 2^-46, refine_max 5, no profiling, library tile choices. */
 void lp_options_default(lp_options* opt);
 
 typedef struct lp_iter_info {
@@ -198,10 +205,11 @@ lp_status lp_destroy(lp_handle* h);
 
 /* ------------------------------------------------------------------------- */
 /* Batched solver: count independent LPs of individual shapes (m_i, n_i), each  */
-/* running the same Section 3 iteration.  One kernel launch advances every     */
-/* active LP by one iteration (a workgroup owns an LP for all phases, LPs taken */
-/* largest m^2 n first); iterations are replayed from a captured hipGraph.     */
-/* FP64 only.                                                                  */
+/* running the same Section 3 iteration.  One iteration of the whole batch is  */
+/* a fixed sequence of launches (normal-matrix tiles, Cholesky panels and      */
+/* trailing updates of every LP at once, per-LP direction and step); several   */
+/* iterations are captured into one hipGraph and replayed.  LPs that stopped   */
+/* skip every launch.  FP64 only.                                              */
 /* ------------------------------------------------------------------------- */
 typedef struct lp_batch lp_batch;
 

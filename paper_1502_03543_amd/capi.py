@@ -43,6 +43,10 @@ class lp_options(C.Structure):
         ("refine_tol", C.c_double),
         ("refine_max", C.c_int32),
         ("profile", C.c_int32),
+        ("syrk_tile", C.c_int32),
+        ("syrk_splits", C.c_int32),
+        ("syrk32_splits", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

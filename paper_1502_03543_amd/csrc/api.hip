@@ -127,6 +127,8 @@ void carve(lp_handle* h, Carver& cv) {
   h->M = cv.take<double>((size_t)h->ldm * (m + 1));  // row m: the right-hand side
   h->diag = cv.take<double>(potrf_diag_elems(m));
   syrk_choose((int)m, (int)n, &h->syrk_tile, &h->syrk_splits);
+  if (h->opt.syrk_tile) h->syrk_tile = h->opt.syrk_tile;
+  if (h->opt.syrk_splits) h->syrk_splits = h->opt.syrk_splits;
   h->syrk_part_n = syrk_part_elems((int)m, h->syrk_tile, h->syrk_splits);
   h->syrk_part = h->syrk_part_n ? cv.take<double>(h->syrk_part_n) : nullptr;
   h->nchunks = gemv_t_chunks(m);
@@ -151,6 +153,7 @@ void carve(lp_handle* h, Carver& cv) {
     h->M32 = cv.take<float>((size_t)h->ld32 * m);
     h->sd32 = cv.take<float>(n);
     syrk_choose_f32((int)m, (int)n, &h->splits32);
+    if (h->opt.syrk32_splits) h->splits32 = h->opt.syrk32_splits;
     const size_t p32 = syrk_part_elems_f32((int)m, h->splits32);
     h->part32 = p32 ? cv.take<float>(p32) : nullptr;
     h->colsq = cv.take<double>(n);
@@ -191,6 +194,10 @@ bool valid_opts(const lp_options* o) {
       (!(o->refine_tol >= 0) || o->refine_max < 0 || !(o->mixed_switch_gap >= 0)))
     return false;
   if (o->tape_capacity < 0) return false;
+  if (o->syrk_tile != 0 && o->syrk_tile != 64 && o->syrk_tile != 128) return false;
+  if (o->syrk_splits < 0 || o->syrk_splits > 64 || o->syrk32_splits < 0 ||
+      o->syrk32_splits > 64 || o->reserved != 0)
+    return false;
   return true;
 }
 

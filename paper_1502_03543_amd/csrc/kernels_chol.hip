@@ -62,6 +62,8 @@ template <> struct RL<float> {
 
 // Panel rows per workgroup: wavefronts 1..3, one row per lane.
 constexpr int kRowsPerWG = 192;
+constexpr int CB = 16;           // column block of the register-resident steps
+constexpr int LDP = NB + 1;      // padded LDS row length
 
 // A zero the compiler cannot see through: LDS reads indexed from it share one
 // base register and carry their constant offsets as immediates.
@@ -69,99 +71,6 @@ __device__ inline int opaque_zero() {
   int z;
   asm volatile("v_mov_b32 %0, 0" : "=v"(z));
   return z;
-}
-
-
-template <typename T>
-struct FactorState {
-  T piv, rinv, myrinv, minp;
-  int fail;
-};
-
-// One right-looking step j of the unblocked factorization of the diagonal
-// block held one row per lane (a[k] = entry (lane, k)); j is a template
-// parameter so every register index is a compile-time constant.
-template <typename T, int J>
-__device__ __forceinline__ void factor_step(T (&a)[NB], FactorState<T>& fs, int nbe, int i,
-                                            T (*col)[NB], int z0) {
-  const bool valid = J < nbe;
-  const T piv = fs.piv, rinv = fs.rinv;
-  const bool bad = !((piv > T(0)) & (piv < T(INFINITY)));
-  fs.fail = (valid & (fs.fail < 0) & bad) ? J : fs.fail;
-  fs.minp = (valid & (piv < fs.minp)) ? piv : fs.minp;
-  const T lij = a[J] * rinv;  // lane J: piv * rinv = L[J][J]
-  a[J] = lij;
-  fs.myrinv = (i == J) ? rinv : fs.myrinv;
-  if constexpr (J + 1 < NB) {
-    col[J & 1][i] = lij;
-    __builtin_amdgcn_wave_barrier();
-    // next pivot straight from lane J+1, off the LDS path; its reciprocal
-    // square root overlaps this step's updates
-    const T pn = RL<T>::rd(a[J + 1], J + 1);
-    const T l1 = RL<T>::rd(lij, J + 1);
-    fs.piv = fma(-l1, l1, pn);
-    const T rnext = RL<T>::rsq(fs.piv);
-    const T* cj = col[J & 1] + z0;
-    // column values in chunks, the next chunk's reads issued ahead of the
-    // current chunk's updates
-    constexpr int CH = 16, K0 = J + 1, NCH = (NB - K0 + CH - 1) / CH;
-    T cv[NCH][CH];
-#pragma unroll
-    for (int kk = 0; kk < CH; ++kk)
-      if (K0 + kk < NB) cv[0][kk] = cj[K0 + kk];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      if (c + 1 < NCH) {
-#pragma unroll
-        for (int kk = 0; kk < CH; ++kk)
-          if (K0 + (c + 1) * CH + kk < NB) cv[c + 1][kk] = cj[K0 + (c + 1) * CH + kk];
-      }
-#pragma unroll
-      for (int kk = 0; kk < CH; ++kk)
-        if (K0 + c * CH + kk < NB) a[K0 + c * CH + kk] = fma(-lij, cv[c][kk], a[K0 + c * CH + kk]);
-    }
-    fs.rinv = rnext;
-  }
-}
-
-template <typename T, int... Js>
-__device__ __forceinline__ void factor_steps(std::integer_sequence<int, Js...>, T (&a)[NB],
-                                             FactorState<T>& fs, int nbe, int i, T (*col)[NB],
-                                             int z0) {
-  (factor_step<T, Js>(a, fs, nbe, i, col, z0), ...);
-}
-
-// One column step c of the panel solve X L11^T = M21 (one row per lane):
-// x[c] /= L[c][c], then x[k] -= x[c] L[k][c] for k > c, with L[k][c] read from
-// lt (row stride NB + 1) in chunks whose reads run ahead of the updates.
-template <typename T, int C>
-__device__ __forceinline__ void solve_step(T (&x)[NB], const T* ltz, const T* dz) {
-  x[C] *= dz[C];
-  if constexpr (C + 1 < NB) {
-    const T* lc = ltz + C * (NB + 1);
-    constexpr int CH = 16, K0 = C + 1, NCH = (NB - K0 + CH - 1) / CH;
-    T cv[NCH][CH];
-#pragma unroll
-    for (int kk = 0; kk < CH; ++kk)
-      if (K0 + kk < NB) cv[0][kk] = lc[K0 + kk];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      if (c + 1 < NCH) {
-#pragma unroll
-        for (int kk = 0; kk < CH; ++kk)
-          if (K0 + (c + 1) * CH + kk < NB) cv[c + 1][kk] = lc[K0 + (c + 1) * CH + kk];
-      }
-#pragma unroll
-      for (int kk = 0; kk < CH; ++kk)
-        if (K0 + c * CH + kk < NB) x[K0 + c * CH + kk] = fma(-x[C], cv[c][kk], x[K0 + c * CH + kk]);
-    }
-  }
-}
-
-template <typename T, int... Cs>
-__device__ __forceinline__ void solve_steps(std::integer_sequence<int, Cs...>, T (&x)[NB],
-                                            const T* ltz, const T* dz) {
-  (solve_step<T, Cs>(x, ltz, dz), ...);
 }
 
 // Workgroup wg of the panel step at column p of an mr x mc lower matrix
@@ -172,56 +81,91 @@ __device__ __forceinline__ void solve_steps(std::integer_sequence<int, Cs...>, T
 // solve rows p + nbe + 192 (wg - 1) ... of L21 in place.  L11 goes to the
 // side block, not to M, because other workgroups of the same launch may still
 // be reading A11 from M; the blocks are copied into M after the last panel.
+//
+// Both phases walk the 64 columns in four blocks of 16 (a runtime loop, so the
+// code stays small): inside a block a lane keeps its 16 entries in registers
+// and the 16 steps are unrolled (compile-time register indices); the block's
+// contribution to the later columns is then applied as a rank-16 update
+// through LDS.
 template <typename T>
 __device__ __forceinline__ void potrf_panel_body(int mr, int mc, T* __restrict__ M, long ld, int p,
                                                  int wg, T* __restrict__ diag_blk, int* fail_out,
                                                  unsigned long long* minp_bits_out) {
-  __shared__ T col[2][NB];             // column j of L11 (lane i writes row i)
-  __shared__ T lt[NB][NB + 1];         // A11 on entry; L11 transposed on exit: lt[c][k] = L[k][c]
-  __shared__ T dinv[NB];
-  __shared__ T S[kRowsPerWG][NB + 1];  // staged panel rows of this workgroup
+  __shared__ T L[NB * LDP];            // A11 on entry, L11 (row-major, lower) after phase 1
+  __shared__ T col[2][CB];             // column of the current step (double-buffered)
+  __shared__ T dinv[NB];               // 1 / L11[j][j]
+  __shared__ T S[kRowsPerWG * LDP];    // staged panel rows of this workgroup
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbe = min(NB, mc - p);
   const bool solve = wg > 0;
   const long r0 = (long)p + nbe + (long)(wg - 1) * kRowsPerWG;
 
   // stage A11 (identity beyond the matrix; upper part never read) and the
-  // workgroup's panel rows, coalesced
+  // workgroup's panel rows (columns clamped to the panel: nbe < 64 only in the
+  // last panel, whose rows below are extra right-hand-side rows), coalesced
   for (int e = tid; e < NB * NB; e += 256) {
     const int r = e / NB, k = e % NB;
     const T v = M[(long)(p + min(r, nbe - 1)) * ld + p + min(k, nbe - 1)];
-    lt[r][k] = (r < nbe && k < nbe) ? v : ((r == k) ? T(1) : T(0));
+    L[r * LDP + k] = (r < nbe && k < nbe) ? v : ((r == k) ? T(1) : T(0));
   }
   if (solve) {
-    // columns clamped to the panel (nbe < 64 only in the last panel, whose
-    // rows below are extra right-hand-side rows)
-    for (int e = tid; e < kRowsPerWG * (NB / 2); e += 256) {
-      const int row = e / (NB / 2), kp = 2 * (e % (NB / 2));
+    for (int e = tid; e < kRowsPerWG * NB; e += 256) {
+      const int row = e / NB, k = e % NB;
       const long gr = min(r0 + row, (long)mr - 1);
-      const T* src = M + gr * ld + p;
-      S[row][kp] = src[min(kp, nbe - 1)];
-      S[row][kp + 1] = src[min(kp + 1, nbe - 1)];
+      S[row * LDP + k] = M[gr * ld + p + min(k, nbe - 1)];
     }
   }
   __syncthreads();
 
   if (wv == 0) {
-    T a[NB];
+    // ---- phase 1: L11 by right-looking steps, lane i = row i ----
     const int i = lane;
+    int fail = -1;
+    T minp = T(INFINITY);
+#pragma unroll 1
+    for (int c0 = 0; c0 < NB; c0 += CB) {
+      T a[CB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) a[k] = lt[i][k];
-    const int z0 = opaque_zero();
-    T piv = RL<T>::rd(a[0], 0);
-    T rinv = RL<T>::rsq(piv);
-    FactorState<T> fs{piv, rinv, T(0), T(INFINITY), -1};
-    factor_steps<T>(std::make_integer_sequence<int, NB>{}, a, fs, nbe, i, col, z0);
-    const int fail = fs.fail;
-    const T minp = fs.minp;
-    const T myrinv = fs.myrinv;
-    __builtin_amdgcn_wave_barrier();
+      for (int jj = 0; jj < CB; ++jj) a[jj] = L[i * LDP + c0 + jj];
+      T piv = RL<T>::rd(a[0], c0);
+      T rinv = RL<T>::rsq(piv);
 #pragma unroll
-    for (int k = 0; k < NB; ++k) lt[k][i] = a[k];
-    dinv[i] = myrinv;
+      for (int jj = 0; jj < CB; ++jj) {
+        const int j = c0 + jj;
+        const bool bad = !((piv > T(0)) & (piv < T(INFINITY)));
+        fail = ((j < nbe) & (fail < 0) & bad) ? j : fail;
+        minp = ((j < nbe) & (piv < minp)) ? piv : minp;
+        const T lij = a[jj] * rinv;  // lane j: piv * rinv = L[j][j]
+        a[jj] = lij;
+        dinv[j] = rinv;              // same value from every lane
+        if (jj + 1 < CB) {
+          if (i > j && i < c0 + CB) col[jj & 1][i - c0] = lij;
+          __builtin_amdgcn_wave_barrier();
+          // next pivot straight from lane j+1; its reciprocal square root
+          // overlaps this step's updates
+          const T pn = RL<T>::rd(a[jj + 1], j + 1);
+          const T l1 = RL<T>::rd(lij, j + 1);
+          piv = fma(-l1, l1, pn);
+          const T rnext = RL<T>::rsq(piv);
+#pragma unroll
+          for (int kk = jj + 1; kk < CB; ++kk) a[kk] = fma(-lij, col[jj & 1][kk], a[kk]);
+          rinv = rnext;
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < CB; ++jj) L[i * LDP + c0 + jj] = a[jj];
+      __builtin_amdgcn_wave_barrier();
+      // rank-16 update of the later columns: L[i][k] -= sum_jj a[jj] L[k][c0 + jj]
+#pragma unroll 1
+      for (int k = c0 + CB; k < NB; ++k) {
+        const T* lk = L + k * LDP + c0;
+        T acc = T(0);
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) acc = fma(a[jj], lk[jj], acc);
+        L[i * LDP + k] -= acc;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
     if (wg == 0 && i == 0) {
       if (fail >= 0) atomicMin(fail_out, p + fail);
       if (minp < T(INFINITY)) {
@@ -235,22 +179,40 @@ __device__ __forceinline__ void potrf_panel_body(int mr, int mc, T* __restrict__
   if (!solve) {
     for (int e = tid; e < NB * NB; e += 256) {
       const int r = e / NB, k = e % NB;
-      if (r < nbe && k <= r) diag_blk[e] = lt[k][r];
+      if (r < nbe && k <= r) diag_blk[e] = L[r * LDP + k];
     }
     return;
   }
   if (wv == 0) return;
+  // ---- phase 2: X L11^T = M21 by forward substitution, lane = panel row ----
   const int row = (wv - 1) * 64 + lane;
+  T* xs = S + row * LDP;
+#pragma unroll 1
+  for (int c0 = 0; c0 < NB; c0 += CB) {
+    T x[CB];
+#pragma unroll
+    for (int jj = 0; jj < CB; ++jj) x[jj] = xs[c0 + jj];
+#pragma unroll
+    for (int jj = 0; jj < CB; ++jj) {
+      x[jj] *= dinv[c0 + jj];
+      const T* lc = L + c0 + jj;
+#pragma unroll
+      for (int kk = jj + 1; kk < CB; ++kk) x[kk] = fma(-x[jj], lc[(c0 + kk) * LDP], x[kk]);
+    }
+#pragma unroll
+    for (int jj = 0; jj < CB; ++jj) xs[c0 + jj] = x[jj];
+#pragma unroll 1
+    for (int k = c0 + CB; k < NB; ++k) {
+      const T* lk = L + k * LDP + c0;
+      T acc = T(0);
+#pragma unroll
+      for (int jj = 0; jj < CB; ++jj) acc = fma(x[jj], lk[jj], acc);
+      xs[k] -= acc;
+    }
+  }
   const long rr = r0 + row;
-  T x[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) x[k] = S[row][k];
-  const int z1 = opaque_zero();
-  solve_steps<T>(std::make_integer_sequence<int, NB>{}, x, &lt[0][0] + z1, dinv + z1);
   if (rr < mr) {
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-      if (k < nbe) M[rr * ld + p + k] = x[k];
+    for (int k = 0; k < nbe; ++k) M[rr * ld + p + k] = xs[k];
   }
 }
 

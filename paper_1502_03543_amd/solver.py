@@ -40,7 +40,8 @@ def workspace(nbytes: int, device) -> tuple[torch.Tensor, int]:
 
 
 def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6,
-            refine_tol=2.0 ** -46, refine_max=5, profile=False) -> capi.lp_options:
+            refine_tol=2.0 ** -46, refine_max=5, profile=False, syrk_tile=0, syrk_splits=0,
+            syrk32_splits=0) -> capi.lp_options:
     o = capi.lp_options()
     capi.lp_options_default(C.byref(o))
     o.alpha = float(alpha)
@@ -50,6 +51,9 @@ def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6
     o.refine_tol = float(refine_tol)
     o.refine_max = int(refine_max)
     o.profile = int(bool(profile))
+    o.syrk_tile = int(syrk_tile)
+    o.syrk_splits = int(syrk_splits)
+    o.syrk32_splits = int(syrk32_splits)
     return o
 
 

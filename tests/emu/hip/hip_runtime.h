@@ -84,7 +84,9 @@ inline void __syncthreads() {
   g_block_bar.wait();
 }
 inline void __threadfence() {}
-inline void __builtin_amdgcn_wave_barrier() {}
+// a wavefront runs in lock-step on the hardware; the emulation makes the
+// points the kernels mark explicit synchronisation points of the wavefront
+inline void __builtin_amdgcn_wave_barrier() { g_wave_bar[threadIdx.x >> 6].wait(); }
 inline void __builtin_amdgcn_sched_barrier(int) {}
 inline void __builtin_amdgcn_s_sleep(int) {}
 

@@ -9,6 +9,8 @@ from paper_1502_03543_amd import capi, lpgen
 
 pytestmark = pytest.mark.gpu
 
+U = 2.0 ** -53
+
 
 @pytest.fixture(scope="module")
 def torch_dev():
@@ -38,11 +40,15 @@ def test_backward_matches_oracle(torch_dev, m, n, K, seed):
     # the oracle's reverse mode on the GPU's own recorded trajectory
     st, go = oracle.backward(lp.A, lp.b, lp.c, 0.9, K, h.tape(K), w)
     assert st == oracle.CONTINUE
+    # dL/dy0 is exactly zero (x_K does not depend on y0 in the residual form:
+    # ds = c - s - A^T M^-1 (b + A D (c - s)) for every y), so it is measured
+    # against the largest gradient instead of its own rounding noise
+    big = max(np.linalg.norm(go[k]) for k in ("Abar", "bbar", "cbar", "x0bar", "s0bar"))
     for key, okey in (("A", "Abar"), ("b", "bbar"), ("c", "cbar"), ("x0", "x0bar"),
                       ("y0", "y0bar"), ("s0", "s0bar")):
         a = g[key].cpu().numpy()
         o = go[okey]
-        scale = max(np.linalg.norm(o), 1e-12 * np.linalg.norm(go["x0bar"]))
+        scale = max(np.linalg.norm(o), 1e-3 * big)
         rel = np.linalg.norm(a - o) / scale
         print(key, rel)
         assert rel <= 1e-6, (key, rel)
@@ -105,6 +111,11 @@ def test_batch_backward_differentiable_config(torch_dev):
         lp = lps[i]
         st, go = oracle.backward(lp.A, lp.b, lp.c, 0.9, K, tapes[i], ws[i])
         assert st == oracle.CONTINUE
+        # two FP64 evaluations of the same step differ by about u kappa(M) in
+        # dy and in the solve with M; kappa(M) reaches 1e10..1e12 by step 30
+        kap = max(np.linalg.cond(oracle.iterate(lp.A, lp.b, lp.c, r[:1024], r[1024:1280],
+                                                r[1280:], 0.9).M) for r in tapes[i][-3:])
+        tol = max(1e-6, 2 * U * kap)
         a0 = int(bt.a_off[i])
         Ai = Ag[a0:a0 + 256 * 1024].reshape(256, 1024)
         bi = g["b"].cpu().numpy()[bt.v_off_m[i]:bt.v_off_m[i] + 256]
@@ -112,5 +123,5 @@ def test_batch_backward_differentiable_config(torch_dev):
         ra = np.linalg.norm(Ai - go["Abar"]) / np.linalg.norm(go["Abar"])
         rb = np.linalg.norm(bi - go["bbar"]) / np.linalg.norm(go["bbar"])
         rc = np.linalg.norm(ci - go["cbar"]) / np.linalg.norm(go["cbar"])
-        print(f"LP {i}: Abar {ra:.1e} bbar {rb:.1e} cbar {rc:.1e}")
-        assert ra <= 1e-6 and rb <= 1e-6, (i, ra, rb)
+        print(f"LP {i}: Abar {ra:.1e} bbar {rb:.1e} cbar {rc:.1e} (kappa {kap:.1e}, tol {tol:.1e})")
+        assert ra <= tol and rb <= tol, (i, ra, rb, tol)
