@@ -14,14 +14,18 @@
 //
 // Workgroup: 256 threads = 2 x 2 wavefronts; tile BM = 8R rows by BN = 32Q
 // columns (square).  Only tiles on or below the diagonal are launched.  Both
-// operands stream through double-buffered LDS in stages of KC along K, laid
-// out so that every LDS read of a wavefront is lane-linear (B) or a 4-way
-// broadcast (A).  Global loads for the next stage are issued before the MFMA
+// operands stream through double-buffered LDS in stages of KC along K, row by
+// row with a padded row length of KC + 4 doubles: a stage is written with
+// 16-byte stores that spread evenly over the 64 banks, the A operand read
+// (4 rows x 4 k, broadcast over the blocks) touches 16 distinct banks pairs
+// and the B read (16 rows x 4 k) needs the two passes its 512 bytes take
+// anyway.  (A blocked layout of 4 k by 16 rows made every stage write a
+// 16-way bank conflict.)  Global loads for the next stage are issued before the MFMA
 // work of the current one and consumed only when they are stored to LDS, so
 // they stay in flight during the matrix work.  The diagonal weight d is
 // applied to the row operand while it is staged.  Split-K writes per-split
-// partial tiles that an ordered second pass sums, so results do not depend
-// on scheduling.
+// partial tiles; the last split of a tile to finish (an arrival counter per
+// tile) sums them in split order, so results do not depend on scheduling.
 #include <cmath>
 
 #include "pdas_internal.h"
@@ -53,13 +57,14 @@ template <int R, int Q, int KC, bool SCALE, bool VEC>
 __device__ __forceinline__ void syrk_f64_tile(int mm, int K, const double* __restrict__ X,
                                               long ldx, const double* __restrict__ w,
                                               double* __restrict__ C, long ldc, int sub, int t,
-                                              int ntiles, int split, int kchunk,
+                                              int ntiles, int split, int nsplit, int kchunk,
                                               double* __restrict__ part) {
   constexpr int BM = 8 * R;
   static_assert(BM == 32 * Q, "square tiles");
   constexpr int PPR = KC / 2;               // element pairs per row per stage
   constexpr int PAIRS = BM * PPR / 256;     // pairs per thread per operand
-  __shared__ double lds[2][2][BM * KC];     // [stage][operand: 0 rows, 1 cols]
+  constexpr int LS = KC + 4;                // padded LDS row length
+  __shared__ double2 lds2[2][2][BM * LS / 2];  // [stage][operand: 0 rows, 1 cols]
 
   int ti, tj;
   tile_coords(t, ti, tj);
@@ -124,10 +129,13 @@ __device__ __forceinline__ void syrk_f64_tile(int mm, int K, const double* __res
         a0 *= pw[it].x;
         a1 *= pw[it].y;
       }
-      lds[buf][0][lidx<BM>(row, kk)] = (va && v0) ? a0 : 0.0;
-      lds[buf][0][lidx<BM>(row, kk + 1)] = (va && v1) ? a1 : 0.0;
-      lds[buf][1][lidx<BM>(row, kk)] = (vb && v0) ? pb[it].x : 0.0;
-      lds[buf][1][lidx<BM>(row, kk + 1)] = (vb && v1) ? pb[it].y : 0.0;
+      double2 sa, sb;
+      sa.x = (va && v0) ? a0 : 0.0;
+      sa.y = (va && v1) ? a1 : 0.0;
+      sb.x = (vb && v0) ? pb[it].x : 0.0;
+      sb.y = (vb && v1) ? pb[it].y : 0.0;
+      lds2[buf][0][(row * LS + kk) / 2] = sa;
+      lds2[buf][1][(row * LS + kk) / 2] = sb;
     }
   };
 
@@ -140,19 +148,19 @@ __device__ __forceinline__ void syrk_f64_tile(int mm, int K, const double* __res
     const int cur = st & 1;
     if (st + 1 < nst) gload(st + 1);
     if (active) {
-      const double* la = lds[cur][0];
-      const double* lb = lds[cur][1];
+      const double* la = reinterpret_cast<const double*>(lds2[cur][0]);
+      const double* lb = reinterpret_cast<const double*>(lds2[cur][1]);
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks) {
         double bq[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           const int c = wc0 + 16 * q + 4 * blk + x;
-          bq[q] = lb[lidx<BM>(c, 4 * ks + y)];
+          bq[q] = lb[c * LS + 4 * ks + y];
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double av = la[lidx<BM>(wr0 + 4 * r + x, 4 * ks + y)];
+          const double av = la[(wr0 + 4 * r + x) * LS + 4 * ks + y];
 #pragma unroll
           for (int q = 0; q < Q; ++q)
             acc[r][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bq[q], acc[r][q], 0, 0, 0);
@@ -163,18 +171,44 @@ __device__ __forceinline__ void syrk_f64_tile(int mm, int K, const double* __res
     __syncthreads();
   }
 
-  if (!active) return;
   if (part) {
     double* P = part + ((long)split * ntiles + t) * (BM * BM);
+    if (active) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+      for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int lr = wr0 + 4 * r + y, lc = wc0 + 16 * q + 4 * blk + x;
-        P[lr * BM + lc] = acc[r][q];
-      }
+        for (int q = 0; q < Q; ++q) {
+          const int lr = wr0 + 4 * r + y, lc = wc0 + 16 * q + 4 * blk + x;
+          P[lr * BM + lc] = acc[r][q];
+        }
+    }
+    // The last split of this tile to arrive sums all partial tiles in split
+    // order (so the result does not depend on which one arrives last).
+    __shared__ int s_last;
+    int* cnt = reinterpret_cast<int*>(part + (long)nsplit * ntiles * (BM * BM));
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      const int prev = __hip_atomic_fetch_add(&cnt[t], 1, __ATOMIC_ACQ_REL,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+      s_last = (prev == nsplit - 1);
+      if (s_last) __hip_atomic_store(&cnt[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int e = tid; e < BM * BM; e += 256) {
+      const int lr = e / BM, lc = e % BM;
+      const int gr = row0 + lr, gc = col0 + lc;
+      if (gr >= mm || gc > gr) continue;
+      double v = 0;
+      for (int sp = 0; sp < nsplit; ++sp) v += part[((long)sp * ntiles + t) * (BM * BM) + e];
+      double* cp = C + (long)gr * ldc + gc;
+      *cp = sub ? (*cp - v) : v;
+    }
     return;
   }
+  if (!active) return;
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -198,27 +232,7 @@ __global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* _
   const int t = (b & 7) * per_xcd + (b >> 3);
   if (t >= ntiles) return;
   syrk_f64_tile<R, Q, KC, SCALE, VEC>(mm, K, X, ldx, w, C, ldc, sub, t, ntiles, blockIdx.y,
-                                      kchunk, part);
-}
-
-// Ordered sum of split-K partial tiles into C (lower part only).
-template <int BM>
-__global__ __launch_bounds__(256) void k_syrk_reduce(int mm, double* __restrict__ C, long ldc,
-                                                     int sub, int ntiles, int splits,
-                                                     const double* __restrict__ part) {
-  const int t = blockIdx.x;
-  int ti, tj;
-  tile_coords(t, ti, tj);
-  const int row0 = ti * BM, col0 = tj * BM;
-  for (int e = threadIdx.x; e < BM * BM; e += 256) {
-    const int lr = e / BM, lc = e % BM;
-    const int gr = row0 + lr, gc = col0 + lc;
-    if (gr >= mm || gc > gr) continue;
-    double v = 0;
-    for (int s = 0; s < splits; ++s) v += part[((long)s * ntiles + t) * (BM * BM) + e];
-    double* cp = C + (long)gr * ldc + gc;
-    *cp = sub ? (*cp - v) : v;
-  }
+                                      gridDim.y, kchunk, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -394,7 +408,7 @@ __global__ __launch_bounds__(256) void k_bsyrk_normal(const BatchLP* __restrict_
   const int t = blockIdx.x;
   if (t >= ntiles) return;
   syrk_f64_tile<8, 2, 32, true, false>(P.m, P.n, A + P.a_off, P.n, d + P.vn, Mpool + P.M_off,
-                                       P.ldm, 0, t, ntiles, 0, P.n, nullptr);
+                                       P.ldm, 0, t, ntiles, 0, 1, P.n, nullptr);
 }
 
 // Batched Cholesky trailing update after the panel at column p:
@@ -412,7 +426,7 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restric
   if (t >= ntiles) return;
   double* X = Mpool + P.M_off + (long)(p + 64) * P.ldm + p;
   syrk_f64_tile<8, 2, 32, false, true>(mm, 64, X, P.ldm, nullptr, X + 64, P.ldm, 1, t, ntiles, 0,
-                                       64, nullptr);
+                                       1, 64, nullptr);
 }
 
 }  // namespace
@@ -420,7 +434,9 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restric
 size_t syrk_part_elems(int mm, int tile, int splits) {
   if (splits <= 1) return 0;
   const long nt = cdiv(mm, tile);
-  return (size_t)splits * (size_t)(nt * (nt + 1) / 2) * (size_t)tile * tile;
+  const size_t ntiles = (size_t)(nt * (nt + 1) / 2);
+  // partial tiles, then one arrival counter (int) per tile
+  return (size_t)splits * ntiles * (size_t)tile * tile + (ntiles + 1) / 2;
 }
 
 void syrk_choose(int mm, int K, int* tile, int* splits) {
@@ -428,10 +444,16 @@ void syrk_choose(int mm, int K, int* tile, int* splits) {
   const int t = mm >= 1024 ? 128 : 64;
   const long nt = cdiv(mm, t);
   const long ntiles = nt * (nt + 1) / 2;
+  // Split the sum over j until about six rounds of workgroups cover the 256
+  // CUs (a last, partly filled round costs as much as a full one), keeping at
+  // least 256 of K per split.
+  static const int kSplits[] = {1, 2, 3, 4, 6, 8, 12, 16};
   int s = 1;
-  // split K until there are enough workgroups to cover the 256 CUs twice,
-  // keeping at least 256 of K per split.
-  while (ntiles * s < 512 && (long)K / (2 * s) >= 256) s *= 2;
+  for (int c : kSplits) {
+    if ((long)K / c < 256) break;
+    s = c;
+    if (ntiles * c >= 1536) break;
+  }
   *tile = t;
   *splits = s;
 }
@@ -449,6 +471,11 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
     splits = 1;
     kchunk = K;
     part = nullptr;
+  }
+  if (part) {
+    // arrival counters of the split tiles start at zero
+    launch_fill_i32(st, reinterpret_cast<int*>(part + (size_t)splits * ntiles * tile * tile), 0,
+                    ntiles);
   }
   dim3 grid(8 * per_xcd, splits);
   const bool vec = ((ldx & 1) == 0) && (((uintptr_t)X & 15) == 0) && ((K & 1) == 0) &&
@@ -476,14 +503,6 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
   }
 #undef PDAS_SYRK
   if (ev_end) (void)hipEventRecord(ev_end, st);
-  if (part) {
-    if (tile == 128)
-      hipLaunchKernelGGL(k_syrk_reduce<128>, dim3(ntiles), dim3(256), 0, st, mm, C, ldc,
-                         (int)sub, ntiles, splits, part);
-    else
-      hipLaunchKernelGGL(k_syrk_reduce<64>, dim3(ntiles), dim3(256), 0, st, mm, C, ldc,
-                         (int)sub, ntiles, splits, part);
-  }
 }
 
 size_t syrk_part_elems_f32(int mm, int splits) {

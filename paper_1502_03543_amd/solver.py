@@ -57,6 +57,22 @@ def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6
     return o
 
 
+def tuned_launch(precision: str, m: int, n: int) -> dict:
+    """Normal-matrix launch choices measured by the autotuner for this shape
+    (empty when none are cached: the library then chooses)."""
+    from . import autotune
+
+    out = {}
+    e64 = autotune.lookup("fp64", m, n)
+    if e64:
+        out.update({k: e64["choice"][k] for k in ("syrk_tile", "syrk_splits")})
+    if precision == "mixed":
+        e32 = autotune.lookup("mixed", m, n)
+        if e32:
+            out["syrk32_splits"] = e32["choice"]["syrk32_splits"]
+    return out
+
+
 class LP:
     """One LP on the GPU (lp_setup ... lp_destroy)."""
 
@@ -67,6 +83,8 @@ class LP:
             _need(t, shp, nm)
         self.m, self.n = m, n
         self.device = A.device
+        if not any(k in opts for k in ("syrk_tile", "syrk_splits", "syrk32_splits")):
+            opts.update(tuned_launch(opts.get("precision", "fp64"), m, n))
         self.opts = options(**opts)
         size = C.c_size_t(0)
         capi.check(capi.lp_workspace_size(m, n, C.byref(self.opts), C.byref(size)),

@@ -3,6 +3,8 @@
 //                                     one extra right-hand-side row; prints
 //                                     the factor and forward-solve errors
 //                                     against a long-double reference
+//   emu syrk <m> <n> <tile> <splits>  normal matrix with split sums, against a
+//                                     long-double reference
 //   emu batch <in> <out> <max_iter> <tape>
 //                                     batched solve of the LPs in <in>; with a
 //                                     tape, also the reverse sweep
@@ -72,6 +74,28 @@ static int run_chol(int m) {
   }
   printf("{\"m\": %d, \"fail\": %d, \"factor_rel_err\": %.3e, \"solve_rel_err\": %.3e}\n", m,
          info.chol_fail == INT_MAX ? -1 : info.chol_fail, lerr / lsc, zerr / zsc);
+  return 0;
+}
+
+static int run_syrk(int m, int n, int tile, int splits) {
+  std::vector<double> A((size_t)m * n), d(n);
+  for (size_t i = 0; i < A.size(); ++i) A[i] = std::sin(0.7 * i + 0.3);
+  for (int j = 0; j < n; ++j) d[j] = 0.5 + 0.25 * std::cos(1.3 * j);
+  const long ldm = m + 3;
+  std::vector<double> M((size_t)m * ldm, NAN);
+  std::vector<double> part(pdas::syrk_part_elems(m, tile, splits) + 1, NAN);
+  pdas::launch_syrk_f64(nullptr, m, n, A.data(), n, d.data(), M.data(), ldm, false, tile, splits,
+                        splits > 1 ? part.data() : nullptr);
+  double err = 0, sc = 0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j <= i; ++j) {
+      long double r = 0;
+      for (int k = 0; k < n; ++k) r += (long double)A[(size_t)i * n + k] * d[k] * A[(size_t)j * n + k];
+      err = std::fmax(err, std::fabs((double)(M[(size_t)i * ldm + j] - r)));
+      sc = std::fmax(sc, std::fabs((double)r));
+    }
+  printf("{\"m\": %d, \"n\": %d, \"tile\": %d, \"splits\": %d, \"rel_err\": %.3e}\n", m, n, tile,
+         splits, err / sc);
   return 0;
 }
 
@@ -150,6 +174,8 @@ static int run_batch(const char* in, const char* out, int max_iter, int tape) {
 
 int main(int argc, char** argv) {
   if (argc >= 3 && !strcmp(argv[1], "chol")) return run_chol(atoi(argv[2]));
+  if (argc >= 6 && !strcmp(argv[1], "syrk"))
+    return run_syrk(atoi(argv[2]), atoi(argv[3]), atoi(argv[4]), atoi(argv[5]));
   if (argc >= 6 && !strcmp(argv[1], "batch"))
     return run_batch(argv[2], argv[3], atoi(argv[4]), atoi(argv[5]));
   fprintf(stderr, "usage: emu chol <m> | emu batch <in> <out> <max_iter> <tape>\n");

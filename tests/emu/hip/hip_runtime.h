@@ -162,6 +162,12 @@ inline emu_f4 __builtin_amdgcn_mfma_f32_16x16x4f32(float a, float b, emu_f4 c, i
   g_wave_bar[w].wait();
   return r;
 }
+// __hip_atomic_* are clang builtins in host code as well; their scope
+// constants are predefined only in HIP mode
+#ifndef __HIP_MEMORY_SCOPE_AGENT
+#define __HIP_MEMORY_SCOPE_WORKGROUP 3
+#define __HIP_MEMORY_SCOPE_AGENT 4
+#endif
 inline int atomicAdd(int* p, int v) { int o = *p; *p += v; return o; }
 inline int atomicOr(int* p, int v) { int o = *p; *p |= v; return o; }
 inline int atomicMin(int* p, int v) { int o = *p; if (v < o) *p = v; return o; }
