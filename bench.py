@@ -257,6 +257,9 @@ def main():
     gflops_s4s5 = (tot["iterations"] * (syrk_flops(m, n) + potrf_flops(m))
                    / ((tot["normal_ms"] + tot["potrf_ms"]) * 1e-3) / 1e9)
     traffic = read_traffic(m, n)
+    o = handles[0].opts
+    tile = o.syrk_tile or "library-chosen"
+    splits = o.syrk_splits or "library-chosen"
 
     out = {
         "metric": "LP solves/s (ADA^T + Cholesky GFLOP/s reported alongside)",
@@ -285,7 +288,8 @@ def main():
         },
         "setup_ms": setup_ms,
         "roofline": {
-            "kernel": "k_syrk_f64<16,4> (normal matrix A D A^T, lower tiles, split-K)",
+            "kernel": (f"k_syrk_f64 (normal matrix A D A^T, lower {tile}x{tile} tiles, "
+                       f"split-K {splits})"),
             "bound": "mfma",
             "achieved": achieved_tflops,
             "peak": PEAK_FP64_MFMA_TFLOPS,

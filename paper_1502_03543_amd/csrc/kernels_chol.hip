@@ -34,6 +34,7 @@ constexpr int NB = kTB;  // 64
 
 template <typename T> struct RL;
 template <> struct RL<double> {
+  typedef double2 T2;
   __device__ static double rd(double v, int lane) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)b, lane);
@@ -50,6 +51,7 @@ template <> struct RL<double> {
   }
 };
 template <> struct RL<float> {
+  typedef float2 T2;
   __device__ static float rd(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
   }
@@ -101,18 +103,53 @@ __device__ __forceinline__ void potrf_panel_body(int mr, int mc, T* __restrict__
   const long r0 = (long)p + nbe + (long)(wg - 1) * kRowsPerWG;
 
   // stage A11 (identity beyond the matrix; upper part never read) and the
-  // workgroup's panel rows (columns clamped to the panel: nbe < 64 only in the
-  // last panel, whose rows below are extra right-hand-side rows), coalesced
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, k = e % NB;
-    const T v = M[(long)(p + min(r, nbe - 1)) * ld + p + min(k, nbe - 1)];
-    L[r * LDP + k] = (r < nbe && k < nbe) ? v : ((r == k) ? T(1) : T(0));
-  }
-  if (solve) {
-    for (int e = tid; e < kRowsPerWG * NB; e += 256) {
-      const int row = e / NB, k = e % NB;
-      const long gr = min(r0 + row, (long)mr - 1);
-      S[row * LDP + k] = M[gr * ld + p + min(k, nbe - 1)];
+  // workgroup's panel rows, coalesced; full panels with 16-byte loads that are
+  // all issued before the first LDS store
+  if (nbe == NB) {
+    typedef typename RL<T>::T2 T2;
+    constexpr int PA = NB * NB / 2 / 256, PS = kRowsPerWG * NB / 2 / 256;
+    T2 va[PA], vs[PS];
+#pragma unroll
+    for (int it = 0; it < PA; ++it) {
+      const int e = tid + 256 * it, r = e / (NB / 2), kp = 2 * (e % (NB / 2));
+      va[it] = *reinterpret_cast<const T2*>(M + (long)(p + r) * ld + p + kp);
+    }
+    if (solve) {
+#pragma unroll
+      for (int it = 0; it < PS; ++it) {
+        const int e = tid + 256 * it, row = e / (NB / 2), kp = 2 * (e % (NB / 2));
+        const long gr = min(r0 + row, (long)mr - 1);
+        vs[it] = *reinterpret_cast<const T2*>(M + gr * ld + p + kp);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < PA; ++it) {
+      const int e = tid + 256 * it, r = e / (NB / 2), kp = 2 * (e % (NB / 2));
+      L[r * LDP + kp] = va[it].x;
+      L[r * LDP + kp + 1] = va[it].y;
+    }
+    if (solve) {
+#pragma unroll
+      for (int it = 0; it < PS; ++it) {
+        const int e = tid + 256 * it, row = e / (NB / 2), kp = 2 * (e % (NB / 2));
+        S[row * LDP + kp] = vs[it].x;
+        S[row * LDP + kp + 1] = vs[it].y;
+      }
+    }
+  } else {
+    // last, partial panel (its rows below are extra right-hand-side rows):
+    // columns clamped to the panel, identity beyond it
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int r = e / NB, k = e % NB;
+      const T v = M[(long)(p + min(r, nbe - 1)) * ld + p + min(k, nbe - 1)];
+      L[r * LDP + k] = (r < nbe && k < nbe) ? v : ((r == k) ? T(1) : T(0));
+    }
+    if (solve) {
+      for (int e = tid; e < kRowsPerWG * NB; e += 256) {
+        const int row = e / NB, k = e % NB;
+        const long gr = min(r0 + row, (long)mr - 1);
+        S[row * LDP + k] = M[gr * ld + p + min(k, nbe - 1)];
+      }
     }
   }
   __syncthreads();
@@ -155,14 +192,19 @@ __device__ __forceinline__ void potrf_panel_body(int mr, int mc, T* __restrict__
 #pragma unroll
       for (int jj = 0; jj < CB; ++jj) L[i * LDP + c0 + jj] = a[jj];
       __builtin_amdgcn_wave_barrier();
-      // rank-16 update of the later columns: L[i][k] -= sum_jj a[jj] L[k][c0 + jj]
+      // rank-16 update of the later columns, four at a time:
+      // L[i][k] -= sum_jj a[jj] L[k][c0 + jj]
 #pragma unroll 1
-      for (int k = c0 + CB; k < NB; ++k) {
-        const T* lk = L + k * LDP + c0;
-        T acc = T(0);
+      for (int k = c0 + CB; k < NB; k += 4) {
+        T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int jj = 0; jj < CB; ++jj) acc = fma(a[jj], lk[jj], acc);
-        L[i * LDP + k] -= acc;
+        for (int u = 0; u < 4; ++u) {
+          const T* lk = L + (k + u) * LDP + c0;
+#pragma unroll
+          for (int jj = 0; jj < CB; ++jj) acc[u] = fma(a[jj], lk[jj], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) L[i * LDP + k + u] -= acc[u];
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -183,36 +225,43 @@ __device__ __forceinline__ void potrf_panel_body(int mr, int mc, T* __restrict__
     }
     return;
   }
-  if (wv == 0) return;
-  // ---- phase 2: X L11^T = M21 by forward substitution, lane = panel row ----
-  const int row = (wv - 1) * 64 + lane;
-  T* xs = S + row * LDP;
+  if (wv != 0) {
+    // ---- phase 2: X L11^T = M21 by forward substitution, lane = panel row ----
+    const int row = (wv - 1) * 64 + lane;
+    T* xs = S + row * LDP;
 #pragma unroll 1
-  for (int c0 = 0; c0 < NB; c0 += CB) {
-    T x[CB];
+    for (int c0 = 0; c0 < NB; c0 += CB) {
+      T x[CB];
 #pragma unroll
-    for (int jj = 0; jj < CB; ++jj) x[jj] = xs[c0 + jj];
+      for (int jj = 0; jj < CB; ++jj) x[jj] = xs[c0 + jj];
 #pragma unroll
-    for (int jj = 0; jj < CB; ++jj) {
-      x[jj] *= dinv[c0 + jj];
-      const T* lc = L + c0 + jj;
+      for (int jj = 0; jj < CB; ++jj) {
+        x[jj] *= dinv[c0 + jj];
+        const T* lc = L + c0 + jj;
 #pragma unroll
-      for (int kk = jj + 1; kk < CB; ++kk) x[kk] = fma(-x[jj], lc[(c0 + kk) * LDP], x[kk]);
-    }
+        for (int kk = jj + 1; kk < CB; ++kk) x[kk] = fma(-x[jj], lc[(c0 + kk) * LDP], x[kk]);
+      }
 #pragma unroll
-    for (int jj = 0; jj < CB; ++jj) xs[c0 + jj] = x[jj];
+      for (int jj = 0; jj < CB; ++jj) xs[c0 + jj] = x[jj];
 #pragma unroll 1
-    for (int k = c0 + CB; k < NB; ++k) {
-      const T* lk = L + k * LDP + c0;
-      T acc = T(0);
+      for (int k = c0 + CB; k < NB; k += 4) {
+        T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int jj = 0; jj < CB; ++jj) acc = fma(x[jj], lk[jj], acc);
-      xs[k] -= acc;
+        for (int u = 0; u < 4; ++u) {
+          const T* lk = L + (k + u) * LDP + c0;
+#pragma unroll
+          for (int jj = 0; jj < CB; ++jj) acc[u] = fma(x[jj], lk[jj], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xs[k + u] -= acc[u];
+      }
     }
   }
-  const long rr = r0 + row;
-  if (rr < mr) {
-    for (int k = 0; k < nbe; ++k) M[rr * ld + p + k] = xs[k];
+  __syncthreads();
+  // solved rows back to M, coalesced
+  for (int e = tid; e < kRowsPerWG * NB; e += 256) {
+    const int row = e / NB, k = e % NB;
+    if (r0 + row < mr && k < nbe) M[(r0 + row) * ld + p + k] = S[row * LDP + k];
   }
 }
 

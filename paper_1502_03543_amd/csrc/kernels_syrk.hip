@@ -444,15 +444,16 @@ void syrk_choose(int mm, int K, int* tile, int* splits) {
   const int t = mm >= 1024 ? 128 : 64;
   const long nt = cdiv(mm, t);
   const long ntiles = nt * (nt + 1) / 2;
-  // Split the sum over j until about six rounds of workgroups cover the 256
-  // CUs (a last, partly filled round costs as much as a full one), keeping at
-  // least 256 of K per split.
+  // Split the sum over j until about three rounds of workgroups cover the 256
+  // CUs, keeping at least 256 of K per split (more splits fill the last round
+  // better but add partial-tile traffic; paper_1502_03543_amd/autotune.py
+  // measures the best count per shape).
   static const int kSplits[] = {1, 2, 3, 4, 6, 8, 12, 16};
   int s = 1;
   for (int c : kSplits) {
     if ((long)K / c < 256) break;
     s = c;
-    if (ntiles * c >= 1536) break;
+    if (ntiles * c >= 768) break;
   }
   *tile = t;
   *splits = s;
