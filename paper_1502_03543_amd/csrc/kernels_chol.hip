@@ -265,12 +265,318 @@ __device__ __forceinline__ void potrf_panel_body(int mr, int mc, T* __restrict__
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_panel(int mr, int mc, T* __restrict__ M, long ld,
-                                                      int p, T* __restrict__ diag,
-                                                      DevInfo* info) {
-  potrf_panel_body<T>(mr, mc, M, ld, p, blockIdx.x, diag + (long)(p / NB) * NB * NB,
-                      &info->chol_fail, reinterpret_cast<unsigned long long*>(&info->min_pivot));
+// ---------------------------------------------------------------------------
+// FP64 panel on the matrix cores.
+//
+// Same step as potrf_panel_body, organised for the matrix cores.
+// v_mfma_f64_4x4x4f64 computes four independent 4 x 4 x 4 products: for block
+// blk, lane i + 4 blk + 16 k supplies A[i][k], lane j + 4 blk + 16 k supplies
+// B[k][j] and lane j + 4 blk + 16 i receives D[i][j].  A 16 x 16 x 4 product
+// C += A B is four of them: instruction cb takes rows 4 cb .. 4 cb + 3 of A
+// (the same in every block) against the four column blocks of B, so lane l
+// supplies B[l / 16][l % 16] and ends with C[4 cb + l / 16][l % 16] in slot
+// cb.  (The single 16x16x4 FP64 instruction
+// has the same result layout but runs at well under half the rate of the
+// 4x4x4 one on this chip.)  Every wavefront owns rows of the panel in tiles
+// of 16: wavefront 0 the 64 rows of A11 (in L), wavefronts 1..3 TPW tiles of
+// staged panel rows each (in S).  The 64 columns go in four blocks of 16;
+// for block b:
+//   1. every wavefront forms, for each of its tiles, the block's 16 columns
+//      minus the contributions of the columns already finished,
+//        R = X[:, c0:c0+16] - X[:, 0:c0] L[c0:c0+16, 0:c0]^T,
+//      on the matrix cores, transposed (R^T = L_blk X^T, so that R^T in the
+//      result layout is directly the B operand of step 3);
+//   2. wavefront 0 moves the 16 x 16 diagonal sub-block to lanes 0..15 (one
+//      row per lane) and factors it column by column; lanes 16..31 carry the
+//      identity rows through the same steps and so come out as the columns of
+//      the inverse of the sub-block's factor;
+//   3. after one barrier every wavefront multiplies its tiles below the
+//      sub-block by that inverse (X_blk = R L_bb^-T, again transposed on the
+//      matrix cores) and stores them; a second barrier publishes the new
+//      columns for the next block.
+// The row operations are those of the column-by-column factorisation and
+// forward substitution, grouped in 16-column blocks; only the summation
+// order differs.
+typedef double mf4 __attribute__((ext_vector_type(4)));
+constexpr int LDQ = NB + 4;  // padded row length: conflict-free operand reads
+constexpr int YP = CB + 1;   // 16 x 16 sub-block exchange
+constexpr int LIP = CB + 4;  // inverse of the sub-block's factor
+
+// 1/sqrt(p): the hardware estimate (relative error about 2^-23) refined by
+// one second-order step, y (1 + e/2 + 3e^2/8) with e = 1 - p y^2, which
+// leaves an error far below an ulp before the last rounding
+__device__ __forceinline__ double rsq_f64(double p) {
+  const double y = __builtin_amdgcn_rsq(p);
+  const double e = fma(-p * y, y, 1.0);
+  const double h = fma(e, 0.375, 0.5);
+  return fma(y * e, h, y);
+}
+
+template <int TPW>
+struct PanelShape {
+  static constexpr int rows = 3 * 16 * TPW;  // staged panel rows per workgroup
+};
+
+// C (16 x 16, slot cb = rows 4 cb + lane / 16) += A (16 x 4) B (4 x 16) with
+// a[cb] = A[4 cb + lane % 4][lane / 16] and b = B[lane / 16][lane % 16]
+__device__ __forceinline__ mf4 mm16(const double (&a)[4], double b, mf4 c) {
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) c[cb] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[cb], b, c[cb], 0, 0, 0);
+  return c;
+}
+
+template <int TPW>
+__device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restrict__ M, long ld,
+                                                 int p, int wg, double* __restrict__ diag_blk,
+                                                 int* fail_out,
+                                                 unsigned long long* minp_bits_out) {
+  constexpr int RW = PanelShape<TPW>::rows;
+  __shared__ double L[NB * LDQ];   // A11 on entry, L11 (row-major, lower) at the end
+  __shared__ double S[RW * LDQ];   // staged panel rows of this workgroup
+  __shared__ double Y[CB * YP];    // diagonal sub-block, one row per lane
+  __shared__ double LI[CB * LIP];  // LI[c][q] = (L_bb^-1)[c][q]
+  __shared__ double CL[2][CB];     // multipliers of the current step
+  __shared__ double PV[NB];        // pivots, checked after the last block
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int nbe = min(NB, mc - p);
+  const bool solve = wg > 0;
+  const long r0 = (long)p + nbe + (long)(wg - 1) * RW;
+
+  // stage A11 (identity beyond the matrix) and the workgroup's panel rows
+  if (nbe == NB) {
+    constexpr int PA = NB * NB / 2 / 256, PS = RW * NB / 2 / 256;
+    double2 va[PA], vs[PS];
+#pragma unroll
+    for (int it = 0; it < PA; ++it) {
+      const int e = tid + 256 * it, r = e / (NB / 2), kp = 2 * (e % (NB / 2));
+      va[it] = *reinterpret_cast<const double2*>(M + (long)(p + r) * ld + p + kp);
+    }
+    if (solve) {
+#pragma unroll
+      for (int it = 0; it < PS; ++it) {
+        const int e = tid + 256 * it, row = e / (NB / 2), kp = 2 * (e % (NB / 2));
+        const long gr = min(r0 + row, (long)mr - 1);
+        vs[it] = *reinterpret_cast<const double2*>(M + gr * ld + p + kp);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < PA; ++it) {
+      const int e = tid + 256 * it, r = e / (NB / 2), kp = 2 * (e % (NB / 2));
+      *reinterpret_cast<double2*>(L + r * LDQ + kp) = va[it];
+    }
+    if (solve) {
+#pragma unroll
+      for (int it = 0; it < PS; ++it) {
+        const int e = tid + 256 * it, row = e / (NB / 2), kp = 2 * (e % (NB / 2));
+        *reinterpret_cast<double2*>(S + row * LDQ + kp) = vs[it];
+      }
+    }
+  } else {
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int r = e / NB, k = e % NB;
+      const double v = M[(long)(p + min(r, nbe - 1)) * ld + p + min(k, nbe - 1)];
+      L[r * LDQ + k] = (r < nbe && k < nbe) ? v : ((r == k) ? 1.0 : 0.0);
+    }
+    if (solve) {
+      for (int e = tid; e < RW * NB; e += 256) {
+        const int row = e / NB, k = e % NB;
+        const long gr = min(r0 + row, (long)mr - 1);
+        S[row * LDQ + k] = M[gr * ld + p + min(k, nbe - 1)];
+      }
+    }
+  }
+  __syncthreads();
+
+  // this wavefront's rows: NT tiles of 16 starting at own
+  const bool active = wv == 0 || solve;
+  double* own = wv == 0 ? L : S + (wv - 1) * (16 * TPW) * LDQ;
+  constexpr int NT = 4 > TPW ? 4 : TPW;
+  const int ntiles = wv == 0 ? 4 : TPW;
+#pragma unroll 1
+  for (int b = 0; b < NB / CB; ++b) {
+    const int c0 = b * CB;
+    // wavefront 0 needs its tiles from the diagonal sub-block down
+    const int t0 = wv == 0 ? b : 0;
+    mf4 R[NT];
+    if (active) {
+      // the block's columns as staged, then minus the finished columns'
+      // contributions (operands of the next K-step loaded ahead)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          R[t][v] = (t < ntiles) ? own[(16 * t + li) * LDQ + c0 + lq + 4 * v] : 0.0;
+      mf4 acc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mf4{0.0, 0.0, 0.0, 0.0};
+      const int nk = c0 / 4;
+      double a[4], bv[NT];
+      if (nk > 0) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) a[cb] = L[(c0 + 4 * cb + (lane & 3)) * LDQ + lq];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bv[t] = own[(16 * (t < ntiles ? t : 0) + li) * LDQ + lq];
+      }
+      for (int kq = 0; kq < nk; ++kq) {
+        const int kn = min(kq + 1, nk - 1);
+        double an[4], bn[NT];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) an[cb] = L[(c0 + 4 * cb + (lane & 3)) * LDQ + 4 * kn + lq];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bn[t] = own[(16 * (t < ntiles ? t : 0) + li) * LDQ + 4 * kn + lq];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (t < ntiles && t >= t0) acc[t] = mm16(a, bv[t], acc[t]);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) a[cb] = an[cb];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bv[t] = bn[t];
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) R[t] -= acc[t];
+    }
+
+    if (wv == 0) {
+      // the sub-block (tile b) to one row per lane, upper part zeroed; lanes
+      // 16..31 start from the identity rows, lanes 32..63 from zero
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t == b) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Y[li * YP + lq + 4 * v] = R[t][v];
+        }
+      __builtin_amdgcn_wave_barrier();
+      double y[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const double yv = Y[li * YP + c];
+        y[c] = lane < 16 ? (c <= lane ? yv : 0.0) : (lane - 16 == c ? 1.0 : 0.0);
+      }
+      __builtin_amdgcn_wave_barrier();
+      // step jj scales the pivot's column by the pivot's reciprocal square
+      // root and takes it out of the later columns.  The pivot chain runs on
+      // each lane's own diagonal entry (d, updated with its own multiplier,
+      // handed over with one readlane), so only the off-diagonal updates need
+      // the other rows' multipliers: they are broadcast through LDS and
+      // applied one step late, filling the latency of the next pivot's
+      // reciprocal square root.
+      double d = lane < 16 ? Y[li * YP + li] : 0.0;
+      double piv = RL<double>::rd(d, 0);
+      double rinv = rsq_f64(piv);
+      double lprev = 0.0, clp[CB], cln[CB];
+#pragma unroll
+      for (int kk = 0; kk < CB; ++kk) clp[kk] = cln[kk] = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < CB; ++jj) {
+        const double lij = y[jj] * rinv;
+        y[jj] = lij;
+        if (lane == 0) PV[c0 + jj] = piv;
+        double rnext = 0.0;
+        if (jj + 1 < CB) {
+          d = fma(-lij, lij, d);
+          piv = RL<double>::rd(d, jj + 1);
+          rnext = rsq_f64(piv);
+        }
+        // previous step's updates of columns jj + 1 ...
+#pragma unroll
+        for (int kk = jj + 1; kk < CB; ++kk)
+          if (jj >= 1) y[kk] = fma(-lprev, clp[kk], y[kk]);
+        if (jj + 1 < CB) {
+          y[jj + 1] = fma(-lij, RL<double>::rd(lij, jj + 1), y[jj + 1]);
+          if (lane < 16) CL[jj & 1][lane] = lij;
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int kk = jj + 2; kk < CB; ++kk) cln[kk] = CL[jj & 1][kk];
+        }
+        lprev = lij;
+#pragma unroll
+        for (int kk = 0; kk < CB; ++kk) clp[kk] = cln[kk];
+        rinv = rnext;
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) L[(c0 + lane) * LDQ + c0 + c] = y[c];
+      } else if (lane < 32) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) LI[c * LIP + lane - 16] = y[c];
+      }
+    }
+    __syncthreads();
+
+    if (active) {
+      double ai[4][4];
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) ai[kq][cb] = LI[(4 * cb + (lane & 3)) * LIP + 4 * kq + lq];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t < ntiles && (wv != 0 || t > b)) {
+          mf4 x = mf4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kq = 0; kq < 4; ++kq) x = mm16(ai[kq], R[t][kq], x);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) own[(16 * t + li) * LDQ + c0 + lq + 4 * v] = x[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (wv == 0 && wg == 0) {
+    // first failing pivot column and smallest pivot (lane j: column j)
+    const double pv = PV[lane];
+    const bool inb = lane < nbe;
+    int fail = (inb && !((pv > 0.0) & (pv < INFINITY))) ? lane : INT_MAX;
+    double minp = (inb && pv < INFINITY) ? pv : INFINITY;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      fail = min(fail, __shfl_xor(fail, o, 64));
+      const double mo = __shfl_xor(minp, o, 64);
+      minp = mo < minp ? mo : minp;
+    }
+    if (lane == 0) {
+      if (fail != INT_MAX) atomicMin(fail_out, p + fail);
+      if (minp < INFINITY) {
+        const double mp = minp > 0.0 ? minp : 0.0;
+        // positive doubles order like their bit patterns
+        atomicMin(minp_bits_out, (unsigned long long)__double_as_longlong(mp));
+      }
+    }
+  }
+  if (!solve) {
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int r = e / NB, k = e % NB;
+      if (r < nbe && k <= r) diag_blk[e] = L[r * LDQ + k];
+    }
+    return;
+  }
+  for (int e = tid; e < RW * NB; e += 256) {
+    const int row = e / NB, k = e % NB;
+    if (r0 + row < mr && k < nbe) M[(r0 + row) * ld + p + k] = S[row * LDQ + k];
+  }
+}
+
+// FP64 panel rows per workgroup (16-row tiles per wavefront 1..3)
+constexpr int kPanelTPW = 2;
+constexpr int kPanelRows = PanelShape<kPanelTPW>::rows;
+
+__global__ __launch_bounds__(256) void k_potrf_panel_f64(int mr, int mc, double* __restrict__ M,
+                                                          long ld, int p,
+                                                          double* __restrict__ diag,
+                                                          DevInfo* info) {
+  potrf_panel_mfma<kPanelTPW>(mr, mc, M, ld, p, blockIdx.x, diag + (long)(p / NB) * NB * NB,
+                              &info->chol_fail,
+                              reinterpret_cast<unsigned long long*>(&info->min_pivot));
+}
+
+__global__ __launch_bounds__(256) void k_potrf_panel_f32(int mr, int mc, float* __restrict__ M,
+                                                          long ld, int p, float* __restrict__ diag,
+                                                          DevInfo* info) {
+  potrf_panel_body<float>(mr, mc, M, ld, p, blockIdx.x, diag + (long)(p / NB) * NB * NB,
+                          &info->chol_fail,
+                          reinterpret_cast<unsigned long long*>(&info->min_pivot));
 }
 
 // Diagonal blocks from the side buffer into M (lower parts); one workgroup
@@ -302,10 +608,10 @@ __global__ __launch_bounds__(256) void k_bpotrf_panel(const BatchLP* __restrict_
   const BatchLP P = lps[lp];
   if (!go[lp] || p >= P.m) return;
   const int below = P.m - p - min(NB, P.m - p);
-  if ((int)blockIdx.x > (below + kRowsPerWG - 1) / kRowsPerWG) return;
-  potrf_panel_body<double>(P.m, P.m, Mpool + P.M_off, P.ldm, p, blockIdx.x,
-                           diagpool + P.diag_off + (long)(p / NB) * NB * NB, fail + lp,
-                           minp_bits + lp);
+  if ((int)blockIdx.x > (below + kPanelRows - 1) / kPanelRows) return;
+  potrf_panel_mfma<kPanelTPW>(P.m, P.m, Mpool + P.M_off, P.ldm, p, blockIdx.x,
+                              diagpool + P.diag_off + (long)(p / NB) * NB * NB, fail + lp,
+                              minp_bits + lp);
 }
 
 // Batched diagonal blocks into M: LP = blockIdx.y, block blockIdx.x.
@@ -324,9 +630,9 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
                       double* diag) {
   for (int p = 0; p < mc; p += NB) {
     const int nbe = (mc - p) < NB ? (mc - p) : NB;
-    const int grid = 1 + cdiv(mr - p - nbe, kRowsPerWG);
-    hipLaunchKernelGGL(k_potrf_panel<double>, dim3(grid), dim3(256), 0, st, mr, mc, M, ld, p,
-                       diag, info);
+    const int grid = 1 + cdiv(mr - p - nbe, kPanelRows);
+    hipLaunchKernelGGL(k_potrf_panel_f64, dim3(grid), dim3(256), 0, st, mr, mc, M, ld, p, diag,
+                       info);
     if (p + NB < mc) {
       launch_syrk_f64(st, mr - p - NB, NB, M + (long)(p + NB) * ld + p, ld, nullptr,
                       M + (long)(p + NB) * ld + (p + NB), ld, true, 64, 1, nullptr);
@@ -340,7 +646,7 @@ void launch_potrf_f32(hipStream_t st, int m, float* M, long ld, DevInfo* info, f
     const int nbe = (m - p) < NB ? (m - p) : NB;
     const int below = m - p - nbe;
     const int grid = 1 + cdiv(below, kRowsPerWG);
-    hipLaunchKernelGGL(k_potrf_panel<float>, dim3(grid), dim3(256), 0, st, m, m, M, ld, p, diag,
+    hipLaunchKernelGGL(k_potrf_panel_f32, dim3(grid), dim3(256), 0, st, m, m, M, ld, p, diag,
                        info);
     if (below > 0)
       launch_syrk_f32(st, below, NB, M + (long)(p + NB) * ld + p, ld, nullptr,
@@ -353,7 +659,7 @@ void launch_bpotrf_panel(hipStream_t st, int count, int max_m, const BatchLP* lp
                          double* Mpool, double* diagpool, int p, int* fail,
                          unsigned long long* minp_bits) {
   const int below = max_m - p - NB;
-  const int gx = 1 + (below > 0 ? cdiv(below, kRowsPerWG) : 0);
+  const int gx = 1 + (below > 0 ? cdiv(below, kPanelRows) : 0);
   hipLaunchKernelGGL(k_bpotrf_panel, dim3(gx, count), dim3(256), 0, st, lps, go, Mpool, diagpool,
                      p, fail, minp_bits);
 }
