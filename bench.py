@@ -258,8 +258,12 @@ def main():
                    / ((tot["normal_ms"] + tot["potrf_ms"]) * 1e-3) / 1e9)
     traffic = read_traffic(m, n)
     o = handles[0].opts
-    tile = o.syrk_tile or "library-chosen"
-    splits = o.syrk_splits or "library-chosen"
+    if o.syrk_tile == 0 and o.syrk_splits == 0 and m >= 512 and n >= 1024:
+        kname = ("k_syrk_sk (normal matrix A D A^T, stream-K: 128x128 lower tiles, one equal "
+                 "share of tile-stages per compute unit, v_mfma_f64_16x16x4f64)")
+    else:
+        kname = (f"k_syrk_f64 (normal matrix A D A^T, lower {o.syrk_tile or 'library-chosen'} "
+                 f"tiles, split-K {o.syrk_splits or 'library-chosen'})")
 
     out = {
         "metric": "LP solves/s (ADA^T + Cholesky GFLOP/s reported alongside)",
@@ -288,8 +292,7 @@ def main():
         },
         "setup_ms": setup_ms,
         "roofline": {
-            "kernel": (f"k_syrk_f64 (normal matrix A D A^T, lower {tile}x{tile} tiles, "
-                       f"split-K {splits})"),
+            "kernel": kname,
             "bound": "mfma",
             "achieved": achieved_tflops,
             "peak": PEAK_FP64_MFMA_TFLOPS,

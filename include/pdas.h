@@ -85,11 +85,15 @@ typedef struct lp_options {
                               back (default 5)                                   */
   int32_t profile;         /* non-zero: time each phase with HIP events on the
                               handle's stream (see lp_get_timings)               */
-  int32_t syrk_tile;       /* FP64 normal-matrix workgroup tile: 0 (library's
-                              choice), 64 or 128; see paper_1502_03543_amd/
-                              autotune.py for the measured choice               */
-  int32_t syrk_splits;     /* FP64 normal-matrix split of the sum over j:
-                              0 (library's choice) or 1..64                     */
+  int32_t syrk_tile;       /* FP64 normal-matrix kernel: 0 (library's choice:
+                              the stream-K kernel, 128 x 128 tiles and one
+                              equal share of the work per compute unit, when
+                              m >= 512 and n >= 1024; split-K otherwise), or
+                              the split-K kernel with 64 or 128 tiles; see
+                              paper_1502_03543_amd/autotune.py                   */
+  int32_t syrk_splits;     /* FP64 split-K parts of the sum over j: 0 (library's
+                              choice) or 1..64; non-zero selects split-K (with
+                              128 tiles unless syrk_tile says 64)                */
   int32_t syrk32_splits;   /* FP32 normal-matrix split (MIXED): 0 or 1..64      */
   int32_t reserved;        /* must be 0                                          */
 } lp_options;

@@ -22,7 +22,8 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
 
-FP64_CANDIDATES = [(128, s) for s in (1, 2, 3, 4, 6, 8, 12, 15, 16, 24, 32)] + \
+# (0, 0): the library's choice (the stream-K kernel for large shapes)
+FP64_CANDIDATES = [(0, 0)] + [(128, s) for s in (1, 2, 3, 4, 6, 8, 12, 16)] + \
                   [(64, s) for s in (1, 2, 4)]
 FP32_CANDIDATES = [s for s in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32)]
 

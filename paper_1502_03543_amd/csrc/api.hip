@@ -128,7 +128,11 @@ void carve(lp_handle* h, Carver& cv) {
   h->diag = cv.take<double>(potrf_diag_elems(m));
   syrk_choose((int)m, (int)n, &h->syrk_tile, &h->syrk_splits);
   if (h->opt.syrk_tile) h->syrk_tile = h->opt.syrk_tile;
-  if (h->opt.syrk_splits) h->syrk_splits = h->opt.syrk_splits;
+  if (h->opt.syrk_splits) {
+    // a split count selects the split-K kernels
+    if (h->syrk_tile == 0) h->syrk_tile = 128;
+    h->syrk_splits = h->opt.syrk_splits;
+  }
   h->syrk_part_n = syrk_part_elems((int)m, h->syrk_tile, h->syrk_splits);
   h->syrk_part = h->syrk_part_n ? cv.take<double>(h->syrk_part_n) : nullptr;
   h->nchunks = gemv_t_chunks(m);

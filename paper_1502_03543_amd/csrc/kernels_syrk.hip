@@ -429,9 +429,206 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restric
                                        1, 64, nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Stream-K normal matrix on v_mfma_f64_16x16x4f64 (lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; slot v of the result is
+// D[l / 16 + 4 v][l % 16]).  The 16x16 product has no replicated operand, so
+// a K-step of a wavefront's 64 x 64 block needs 8 LDS reads for 16
+// instructions (the 4x4x4 form needs 20 for the same work); that is what
+// keeps this kernel off the LDS bandwidth limit.
+//
+// Workgroup tile 128 x 128 (2 x 2 wavefronts of 64 x 64), stages of 32 along
+// K through double-buffered LDS rows padded to 34 doubles.  The iteration
+// space (lower tiles x stages, tile-major) is cut into kSkGroups equal
+// contiguous ranges, one per workgroup, so every compute unit gets the same
+// amount of matrix work whatever the number of tiles.  A range covers the
+// end of one tile, whole tiles and the start of another: whole tiles are
+// written directly; a partial tile goes to the workgroup's slot (first or
+// last) and the last of the tile's workgroups to arrive (a counter per tile)
+// adds the slots in workgroup order, so the result does not depend on
+// scheduling.  Consecutive workgroup ids land on different XCDs; the range
+// index is remapped so that each XCD owns one contiguous eighth of the work.
+constexpr int kSkT = 4;                 // 16 x 16 blocks per wavefront side
+constexpr int kSkBM = 32 * kSkT;        // 128
+constexpr int kSkKC = 32;
+constexpr int kSkLS = kSkKC + 2;
+constexpr int kSkGroups = 256;          // one workgroup per compute unit
+
+typedef double sk4 __attribute__((ext_vector_type(4)));
+
+// Tile t over k in [kbeg, kend) into acc (the whole workgroup takes part).
+__device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, long ldx,
+                                        const double* __restrict__ w, int t, int kbeg, int kend,
+                                        sk4 (&acc)[kSkT][kSkT], bool active) {
+  constexpr int PPR = kSkKC / 2;
+  constexpr int PAIRS = kSkBM * PPR / 256;
+  __shared__ __attribute__((aligned(16))) double lds[2][2][kSkBM * kSkLS];
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int row0 = ti * kSkBM, col0 = tj * kSkBM;
+  const int nst = (kend - kbeg + kSkKC - 1) / kSkKC;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr0 = (wv >> 1) * (16 * kSkT), wc0 = (wv & 1) * (16 * kSkT);
+  double2 pa[PAIRS], pb[PAIRS], pw[PAIRS];
+  auto gload = [&](int st) {
+    const int kb = kbeg + st * kSkKC;
+#pragma unroll
+    for (int it = 0; it < PAIRS; ++it) {
+      const int p = tid + 256 * it;
+      const int row = p / PPR, k = kb + 2 * (p % PPR);
+      const long ra = min(row0 + row, mm - 1), rb = min(col0 + row, mm - 1);
+      const int kc = min(k, kend - 2);
+      pa[it] = *reinterpret_cast<const double2*>(X + ra * ldx + kc);
+      pb[it] = *reinterpret_cast<const double2*>(X + rb * ldx + kc);
+      pw[it] = *reinterpret_cast<const double2*>(w + kc);
+    }
+  };
+  auto sstore = [&](int buf, int st) {
+    const int kb = kbeg + st * kSkKC;
+#pragma unroll
+    for (int it = 0; it < PAIRS; ++it) {
+      const int p = tid + 256 * it;
+      const int row = p / PPR, kk = 2 * (p % PPR), k = kb + kk;
+      const bool va = row0 + row < mm, vb = col0 + row < mm;
+      const bool v0 = k < kend, v1 = k + 1 < kend;
+      double2 sa, sb;
+      sa.x = (va && v0) ? pa[it].x * pw[it].x : 0.0;
+      sa.y = (va && v1) ? pa[it].y * pw[it].y : 0.0;
+      sb.x = (vb && v0) ? pb[it].x : 0.0;
+      sb.y = (vb && v1) ? pb[it].y : 0.0;
+      *reinterpret_cast<double2*>(&lds[buf][0][row * kSkLS + kk]) = sa;
+      *reinterpret_cast<double2*>(&lds[buf][1][row * kSkLS + kk]) = sb;
+    }
+  };
+  if (nst > 0) {
+    gload(0);
+    sstore(0, 0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) gload(st + 1);
+    if (active) {
+      const double* la = lds[cur][0];
+      const double* lb = lds[cur][1];
+#pragma unroll
+      for (int ks = 0; ks < kSkKC / 4; ++ks) {
+        double a[kSkT], b[kSkT];
+#pragma unroll
+        for (int r = 0; r < kSkT; ++r) a[r] = la[(wr0 + 16 * r + li) * kSkLS + 4 * ks + lk];
+#pragma unroll
+        for (int c = 0; c < kSkT; ++c) b[c] = lb[(wc0 + 16 * c + li) * kSkLS + 4 * ks + lk];
+#pragma unroll
+        for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+          for (int c = 0; c < kSkT; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
+      }
+    }
+    if (st + 1 < nst) sstore(cur ^ 1, st + 1);
+    __syncthreads();
+  }
+}
+
+// C (lower, ldc) = X diag(w) X^T; X rows 16-byte aligned, K even.
+// part: kSkGroups * 2 partial tiles, then one arrival counter per tile
+// (zero on entry; every counter is back at zero when the launch ends).
+__global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __restrict__ X,
+                                                 long ldx, const double* __restrict__ w,
+                                                 double* __restrict__ C, long ldc, int ntiles,
+                                                 double* __restrict__ part) {
+  constexpr int BM = kSkBM, G = kSkGroups;
+  const int S = (K + kSkKC - 1) / kSkKC;
+  const long W = (long)ntiles * S;
+  const int g = (int)((blockIdx.x & 7) * (G / 8) + (blockIdx.x >> 3));
+  auto bnd = [&](long gg) { return gg * W / G; };
+  const long b0 = bnd(g), b1 = bnd(g + 1);
+  int* cnt = reinterpret_cast<int*>(part + (long)G * 2 * BM * BM);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr0 = (wv >> 1) * (16 * kSkT), wc0 = (wv & 1) * (16 * kSkT);
+  __shared__ int s_last;
+  for (long it = b0; it < b1;) {
+    const int t = (int)(it / S), s0 = (int)(it % S);
+    const int s1 = (int)min((long)S, s0 + (b1 - it));
+    int ti, tj;
+    tile_coords(t, ti, tj);
+    const int row0 = ti * BM, col0 = tj * BM;
+    // wavefronts of a diagonal tile whose block lies above the diagonal idle
+    const bool active = !(ti == tj && wr0 + 16 * kSkT <= wc0);
+    sk4 acc[kSkT][kSkT];
+#pragma unroll
+    for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+      for (int c = 0; c < kSkT; ++c) acc[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
+    sk_tile(mm, X, ldx, w, t, s0 * kSkKC, min(K, s1 * kSkKC), acc, active);
+    const bool whole = (s0 == 0 && s1 == S);
+    double* P = part + ((long)g * 2 + (it == b0 ? 0 : 1)) * (BM * BM);
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+        for (int c = 0; c < kSkT; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lr = wr0 + 16 * r + lk + 4 * v, lc = wc0 + 16 * c + li;
+            if (whole) {
+              const int gr = row0 + lr, gc = col0 + lc;
+              if (gr < mm && gc <= gr) C[(long)gr * ldc + gc] = acc[r][c][v];
+            } else {
+              P[lr * BM + lc] = acc[r][c][v];
+            }
+          }
+    }
+    if (!whole) {
+      // the workgroups whose ranges meet tile t
+      const long xs = (long)t * S, xe = xs + S - 1;
+      long glo = xs * G / W, ghi = xe * G / W;
+      while (bnd(glo) > xs) --glo;
+      while (bnd(glo + 1) <= xs) ++glo;
+      while (bnd(ghi) > xe) --ghi;
+      while (bnd(ghi + 1) <= xe) ++ghi;
+      const int nseg = (int)(ghi - glo + 1);
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) {
+        const int prev = __hip_atomic_fetch_add(&cnt[t], 1, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == nseg - 1);
+        if (s_last) __hip_atomic_store(&cnt[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+      if (s_last) {
+        __threadfence();
+        for (int e = tid; e < BM * BM; e += 256) {
+          const int lr = e / BM, lc = e % BM;
+          const int gr = row0 + lr, gc = col0 + lc;
+          if (gr >= mm || gc > gr) continue;
+          double v = 0.0;
+          for (long gg = glo; gg <= ghi; ++gg) {
+            // slot 0 when tile t is where workgroup gg's range starts
+            const int sl = (bnd(gg) / S == t) ? 0 : 1;
+            v += part[(gg * 2 + sl) * (BM * BM) + e];
+          }
+          C[(long)gr * ldc + gc] = v;
+        }
+      }
+      __syncthreads();
+    }
+    it += s1 - s0;
+  }
+}
+
 }  // namespace
 
 size_t syrk_part_elems(int mm, int tile, int splits) {
+  if (tile == 0) {
+    // stream-K: two partial tiles per workgroup, then the tile counters
+    const long nt = cdiv(mm, kSkBM);
+    const size_t ntiles = (size_t)(nt * (nt + 1) / 2);
+    return (size_t)kSkGroups * 2 * kSkBM * kSkBM + (ntiles + 1) / 2;
+  }
   if (splits <= 1) return 0;
   const long nt = cdiv(mm, tile);
   const size_t ntiles = (size_t)(nt * (nt + 1) / 2);
@@ -440,7 +637,13 @@ size_t syrk_part_elems(int mm, int tile, int splits) {
 }
 
 void syrk_choose(int mm, int K, int* tile, int* splits) {
-  // Large outputs: 128 x 128 tiles; small outputs: 64 x 64 for parallelism.
+  // Large problems: the stream-K kernel (tile 0).
+  if (mm >= 512 && K >= 1024) {
+    *tile = 0;
+    *splits = 1;
+    return;
+  }
+  // Otherwise split-K: 128 x 128 tiles for large outputs, 64 x 64 for small.
   const int t = mm >= 1024 ? 128 : 64;
   const long nt = cdiv(mm, t);
   const long ntiles = nt * (nt + 1) / 2;
@@ -463,6 +666,24 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
                      double* C, long ldc, bool sub, int tile, int splits, double* part,
                      hipEvent_t ev_begin, hipEvent_t ev_end) {
   if (mm <= 0) return;
+  const bool vec = ((ldx & 1) == 0) && (((uintptr_t)X & 15) == 0) && ((K & 1) == 0) &&
+                   (!w || (((uintptr_t)w & 15) == 0));
+  if (tile == 0) {
+    if (w && !sub && vec && part && K >= 2) {
+      const int nt = cdiv(mm, kSkBM);
+      const int ntiles = nt * (nt + 1) / 2;
+      launch_fill_i32(st, reinterpret_cast<int*>(part + (size_t)kSkGroups * 2 * kSkBM * kSkBM), 0,
+                      ntiles);
+      if (ev_begin) (void)hipEventRecord(ev_begin, st);
+      hipLaunchKernelGGL(k_syrk_sk, dim3(kSkGroups), dim3(256), 0, st, mm, K, X, ldx, w, C, ldc,
+                         ntiles, part);
+      if (ev_end) (void)hipEventRecord(ev_end, st);
+      return;
+    }
+    // operands the stream-K kernel does not take: one 64-tile pass
+    tile = 64;
+    splits = 1;
+  }
   const int nt = cdiv(mm, tile);
   const int ntiles = nt * (nt + 1) / 2;
   const int per_xcd = cdiv(ntiles, 8);
@@ -479,8 +700,6 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
                     ntiles);
   }
   dim3 grid(8 * per_xcd, splits);
-  const bool vec = ((ldx & 1) == 0) && (((uintptr_t)X & 15) == 0) && ((K & 1) == 0) &&
-                   (!w || (((uintptr_t)w & 15) == 0));
   if (ev_begin) (void)hipEventRecord(ev_begin, st);
 #define PDAS_SYRK(R_, Q_, KC_, S_, V_)                                                        \
   hipLaunchKernelGGL((k_syrk_f64<R_, Q_, KC_, S_, V_>), grid, dim3(256), 0, st, mm, K, X, ldx, \

@@ -87,8 +87,11 @@ void launch_lower_f32_to_f64(hipStream_t st, long m, const float* L32, long ld32
 
 // --- normal matrix (kernels_syrk.hip) --------------------------------------
 // C (row-major lower, ldc) = X diag(w) X^T (w may be null) or, when sub,
-// C -= X X^T.  X: mm rows of length K, row stride ldx.  part: split-K scratch
-// (may be null when splits == 1).
+// C -= X X^T.  X: mm rows of length K, row stride ldx.  tile 64 or 128:
+// split-K over `splits` parts; tile 0: the stream-K kernel (X diag(w) X^T
+// only, 16-byte aligned rows and even K; anything else falls back to one
+// 64-tile pass).  part: syrk_part_elems(mm, tile, splits) doubles of scratch
+// (may be null when that is 0).
 void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, const double* w,
                      double* C, long ldc, bool sub, int tile, int splits, double* part,
                      hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);

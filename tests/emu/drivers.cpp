@@ -3,7 +3,7 @@
 //                                     one extra right-hand-side row; prints
 //                                     the factor and forward-solve errors
 //                                     against a long-double reference
-//   emu syrk <m> <n> <tile> <splits>  normal matrix with split sums, against a
+//   emu syrk <m> <n> <tile> <splits>  normal matrix (tile 0: stream-K), against a
 //                                     long-double reference
 //   emu batch <in> <out> <max_iter> <tape>
 //                                     batched solve of the LPs in <in>; with a
@@ -85,7 +85,7 @@ static int run_syrk(int m, int n, int tile, int splits) {
   std::vector<double> M((size_t)m * ldm, NAN);
   std::vector<double> part(pdas::syrk_part_elems(m, tile, splits) + 1, NAN);
   pdas::launch_syrk_f64(nullptr, m, n, A.data(), n, d.data(), M.data(), ldm, false, tile, splits,
-                        splits > 1 ? part.data() : nullptr);
+                        (tile == 0 || splits > 1) ? part.data() : nullptr);
   double err = 0, sc = 0;
   for (int i = 0; i < m; ++i)
     for (int j = 0; j <= i; ++j) {

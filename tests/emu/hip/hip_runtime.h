@@ -138,6 +138,28 @@ inline double __builtin_amdgcn_mfma_f64_4x4x4f64(double a, double b, double c, i
   return acc;
 }
 
+typedef double emu_d4 __attribute__((ext_vector_type(4)));
+// v_mfma_f64_16x16x4f64: lane l holds A[i = l % 16][k = l / 16],
+// B[k = l / 16][j = l % 16]; result slot v of lane l is D[l / 16 + 4 v][l % 16].
+inline emu_d4 __builtin_amdgcn_mfma_f64_16x16x4f64(double a, double b, emu_d4 c, int, int, int) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  g_wave_buf[w][l] = emu_bits(a);
+  g_wave_buf2[w][l] = emu_bits(b);
+  g_wave_bar[w].wait();
+  const int j = l % 16;
+  emu_d4 r = c;
+  for (int v = 0; v < 4; ++v) {
+    const int i = l / 16 + 4 * v;
+    double acc = r[v];
+    for (int k = 0; k < 4; ++k)
+      acc = std::fma(emu_from<double>(g_wave_buf[w][i + 16 * k]),
+                     emu_from<double>(g_wave_buf2[w][j + 16 * k]), acc);
+    r[v] = acc;
+  }
+  g_wave_bar[w].wait();
+  return r;
+}
+
 inline double __builtin_amdgcn_rsq(double p) { return 1.0 / std::sqrt(p); }
 inline float __builtin_amdgcn_rsqf(float p) { return 1.0f / std::sqrt(p); }
 inline float __int_as_float(int v) { return emu_from<float>((uint32_t)v); }
