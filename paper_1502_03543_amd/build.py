@@ -33,6 +33,10 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # gfx950: keep packed-FP32 instructions out of generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs: with accumulation registers
+    # the FP64 16x16x4 instruction ran at half rate on gfx950 (36 vs 77 TF in
+    # a register-only loop)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

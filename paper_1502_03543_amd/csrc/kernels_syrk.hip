@@ -446,8 +446,10 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restric
 // written directly; a partial tile goes to the workgroup's slot (first or
 // last) and the last of the tile's workgroups to arrive (a counter per tile)
 // adds the slots in workgroup order, so the result does not depend on
-// scheduling.  Consecutive workgroup ids land on different XCDs; the range
-// index is remapped so that each XCD owns one contiguous eighth of the work.
+// scheduling; that workgroup adds the other slots to its own segment, still
+// in registers, with lane-contiguous loads.  Consecutive workgroup ids land
+// on different XCDs; the range index is remapped so that each XCD owns one
+// contiguous eighth of the work.
 constexpr int kSkT = 4;                 // 16 x 16 blocks per wavefront side
 constexpr int kSkBM = 32 * kSkT;        // 128
 constexpr int kSkKC = 32;
@@ -564,24 +566,30 @@ __global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __
       for (int c = 0; c < kSkT; ++c) acc[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
     sk_tile(mm, X, ldx, w, t, s0 * kSkKC, min(K, s1 * kSkKC), acc, active);
     const bool whole = (s0 == 0 && s1 == S);
-    double* P = part + ((long)g * 2 + (it == b0 ? 0 : 1)) * (BM * BM);
-    if (active) {
+    if (whole) {
+      if (active) {
 #pragma unroll
-      for (int r = 0; r < kSkT; ++r)
+        for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-        for (int c = 0; c < kSkT; ++c)
+          for (int c = 0; c < kSkT; ++c)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int lr = wr0 + 16 * r + lk + 4 * v, lc = wc0 + 16 * c + li;
-            if (whole) {
-              const int gr = row0 + lr, gc = col0 + lc;
+            for (int v = 0; v < 4; ++v) {
+              const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
               if (gr < mm && gc <= gr) C[(long)gr * ldc + gc] = acc[r][c][v];
-            } else {
-              P[lr * BM + lc] = acc[r][c][v];
             }
-          }
-    }
-    if (!whole) {
+      }
+    } else {
+      // partial tile in register order (lane-contiguous, so both the store and
+      // the reducer's loads are coalesced): element (q = r kSkT + c, v) of
+      // lane l of wavefront wv at ((wv * 16 + q) * 64 + l) * 4 + v
+      double* P = part + ((long)g * 2 + (it == b0 ? 0 : 1)) * (BM * BM);
+      if (active) {
+#pragma unroll
+        for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+          for (int c = 0; c < kSkT; ++c)
+            *reinterpret_cast<sk4*>(P + ((wv * 16 + r * kSkT + c) * 64 + lane) * 4) = acc[r][c];
+      }
       // the workgroups whose ranges meet tile t
       const long xs = (long)t * S, xe = xs + S - 1;
       long glo = xs * G / W, ghi = xe * G / W;
@@ -599,20 +607,46 @@ __global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __
         if (s_last) __hip_atomic_store(&cnt[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       __syncthreads();
-      if (s_last) {
+      if (s_last && active) {
         __threadfence();
-        for (int e = tid; e < BM * BM; e += 256) {
-          const int lr = e / BM, lc = e % BM;
-          const int gr = row0 + lr, gc = col0 + lc;
-          if (gr >= mm || gc > gr) continue;
-          double v = 0.0;
-          for (long gg = glo; gg <= ghi; ++gg) {
+        // sum of the segments in workgroup order; this workgroup's own
+        // segment is still in registers
+        sk4 tot[kSkT][kSkT];
+#pragma unroll
+        for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+          for (int c = 0; c < kSkT; ++c) tot[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
+        for (long gg = glo; gg <= ghi; ++gg) {
+          if (gg == g) {
+#pragma unroll
+            for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+              for (int c = 0; c < kSkT; ++c) tot[r][c] += acc[r][c];
+          } else {
             // slot 0 when tile t is where workgroup gg's range starts
             const int sl = (bnd(gg) / S == t) ? 0 : 1;
-            v += part[(gg * 2 + sl) * (BM * BM) + e];
+            const double* Q = part + (gg * 2 + sl) * (BM * BM);
+            sk4 pv[kSkT][kSkT];
+#pragma unroll
+            for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+              for (int c = 0; c < kSkT; ++c)
+                pv[r][c] = *reinterpret_cast<const sk4*>(Q + ((wv * 16 + r * kSkT + c) * 64 + lane) * 4);
+#pragma unroll
+            for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+              for (int c = 0; c < kSkT; ++c) tot[r][c] += pv[r][c];
           }
-          C[(long)gr * ldc + gc] = v;
         }
+#pragma unroll
+        for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+          for (int c = 0; c < kSkT; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
+              if (gr < mm && gc <= gr) C[(long)gr * ldc + gc] = tot[r][c][v];
+            }
       }
       __syncthreads();
     }
