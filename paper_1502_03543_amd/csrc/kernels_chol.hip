@@ -26,6 +26,7 @@
 #include <utility>
 
 #include "pdas_internal.h"
+#include "syrk_tile.h"
 
 namespace pdas {
 namespace {
@@ -325,18 +326,24 @@ __device__ __forceinline__ mf4 mm16(const double (&a)[4], double b, mf4 c) {
   return c;
 }
 
+// LDS of the panel routine (doubles)
+template <int TPW>
+constexpr int panel_lds_doubles() {
+  return NB * LDQ + PanelShape<TPW>::rows * LDQ + CB * YP + CB * LIP + 2 * CB + NB;
+}
+
 template <int TPW>
 __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restrict__ M, long ld,
                                                  int p, int wg, double* __restrict__ diag_blk,
-                                                 int* fail_out,
-                                                 unsigned long long* minp_bits_out) {
+                                                 int* fail_out, unsigned long long* minp_bits_out,
+                                                 double* lds) {
   constexpr int RW = PanelShape<TPW>::rows;
-  __shared__ double L[NB * LDQ];   // A11 on entry, L11 (row-major, lower) at the end
-  __shared__ double S[RW * LDQ];   // staged panel rows of this workgroup
-  __shared__ double Y[CB * YP];    // diagonal sub-block, one row per lane
-  __shared__ double LI[CB * LIP];  // LI[c][q] = (L_bb^-1)[c][q]
-  __shared__ double CL[2][CB];     // multipliers of the current step
-  __shared__ double PV[NB];        // pivots, checked after the last block
+  double* L = lds;                       // A11 on entry, L11 (row-major, lower) at the end
+  double* S = L + NB * LDQ;              // staged panel rows of this workgroup
+  double* Y = S + RW * LDQ;              // diagonal sub-block, one row per lane
+  double* LI = Y + CB * YP;              // LI[c][q] = (L_bb^-1)[c][q]
+  double(*CL)[CB] = reinterpret_cast<double(*)[CB]>(LI + CB * LIP);  // multipliers of a step
+  double* PV = LI + CB * LIP + 2 * CB;   // pivots, checked after the last block
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int nbe = min(NB, mc - p);
@@ -352,25 +359,23 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
       const int e = tid + 256 * it, r = e / (NB / 2), kp = 2 * (e % (NB / 2));
       va[it] = *reinterpret_cast<const double2*>(M + (long)(p + r) * ld + p + kp);
     }
-    if (solve) {
+    // (workgroup 0 stages rows too, clamped into the matrix, and ignores
+    // them: unconditional staging keeps vs in registers)
 #pragma unroll
-      for (int it = 0; it < PS; ++it) {
-        const int e = tid + 256 * it, row = e / (NB / 2), kp = 2 * (e % (NB / 2));
-        const long gr = min(r0 + row, (long)mr - 1);
-        vs[it] = *reinterpret_cast<const double2*>(M + gr * ld + p + kp);
-      }
+    for (int it = 0; it < PS; ++it) {
+      const int e = tid + 256 * it, row = e / (NB / 2), kp = 2 * (e % (NB / 2));
+      const long gr = min(max(r0 + row, 0L), (long)mr - 1);
+      vs[it] = *reinterpret_cast<const double2*>(M + gr * ld + p + kp);
     }
 #pragma unroll
     for (int it = 0; it < PA; ++it) {
       const int e = tid + 256 * it, r = e / (NB / 2), kp = 2 * (e % (NB / 2));
       *reinterpret_cast<double2*>(L + r * LDQ + kp) = va[it];
     }
-    if (solve) {
 #pragma unroll
-      for (int it = 0; it < PS; ++it) {
-        const int e = tid + 256 * it, row = e / (NB / 2), kp = 2 * (e % (NB / 2));
-        *reinterpret_cast<double2*>(S + row * LDQ + kp) = vs[it];
-      }
+    for (int it = 0; it < PS; ++it) {
+      const int e = tid + 256 * it, row = e / (NB / 2), kp = 2 * (e % (NB / 2));
+      *reinterpret_cast<double2*>(S + row * LDQ + kp) = vs[it];
     }
   } else {
     for (int e = tid; e < NB * NB; e += 256) {
@@ -566,9 +571,54 @@ __global__ __launch_bounds__(256) void k_potrf_panel_f64(int mr, int mc, double*
                                                           long ld, int p,
                                                           double* __restrict__ diag,
                                                           DevInfo* info) {
+  __shared__ __attribute__((aligned(16))) double lds[panel_lds_doubles<kPanelTPW>()];
   potrf_panel_mfma<kPanelTPW>(mr, mc, M, ld, p, blockIdx.x, diag + (long)(p / NB) * NB * NB,
                               &info->chol_fail,
-                              reinterpret_cast<unsigned long long*>(&info->min_pivot));
+                              reinterpret_cast<unsigned long long*>(&info->min_pivot), lds);
+}
+
+// The fused Cholesky step at column p.  Workgroups 0 .. npw_need - 1 run the
+// panel step; workgroups from npw (a multiple of 8, so that the update's
+// tile order stays XCD-aware) apply the previous panel (columns p - NB ..
+// p - 1) to the trailing columns from p + NB on.  The two write disjoint
+// parts of M (the panel its own columns, the update the columns beyond), and
+// the previous panel's contribution to columns p .. p + NB - 1 was applied
+// by its own column update (k_chol_col0) before this launch, so the panel
+// factorisation no longer waits for the whole trailing update.
+constexpr int kStepLds = panel_lds_doubles<kPanelTPW>() > 2 * syrk_tile_lds2<8, 32>()
+                             ? panel_lds_doubles<kPanelTPW>()
+                             : 2 * syrk_tile_lds2<8, 32>();
+
+__global__ __launch_bounds__(256) void k_chol_step(int mr, int mc, double* __restrict__ M, long ld,
+                                                   int p, double* __restrict__ diag,
+                                                   DevInfo* info, int npw_need, int npw,
+                                                   int ntiles, int per_xcd) {
+  __shared__ __attribute__((aligned(16))) double lds[kStepLds];
+  const int b = blockIdx.x;
+  if (b < npw) {
+    if (b >= npw_need) return;
+    potrf_panel_mfma<kPanelTPW>(mr, mc, M, ld, p, b, diag + (long)(p / NB) * NB * NB,
+                                &info->chol_fail,
+                                reinterpret_cast<unsigned long long*>(&info->min_pivot), lds);
+    return;
+  }
+  const int bb = b - npw;
+  const int t = (bb & 7) * per_xcd + (bb >> 3);
+  if (t >= ntiles) return;
+  const int q = p + NB;
+  syrk_f64_tile<8, 2, 32, false, true>(mr - q, NB, M + (long)q * ld + (p - NB), ld, nullptr,
+                                       M + (long)q * ld + q, ld, 1, t, ntiles, 0, 1, NB, nullptr,
+                                       reinterpret_cast<double2*>(lds));
+}
+
+// Update of the next panel's columns p + NB .. p + 2 NB - 1 (all rows from
+// p + NB) with panel p: the first tile column of the trailing update.
+__global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ M, long ld, int p) {
+  __shared__ double2 lds2[syrk_tile_lds2<8, 32>()];
+  const int q = p + NB, ti = blockIdx.x;
+  syrk_f64_tile<8, 2, 32, false, true>(mr - q, NB, M + (long)q * ld + p, ld, nullptr,
+                                       M + (long)q * ld + q, ld, 1, ti * (ti + 1) / 2, 0, 0, 1, NB,
+                                       nullptr, lds2);
 }
 
 __global__ __launch_bounds__(256) void k_potrf_panel_f32(int mr, int mc, float* __restrict__ M,
@@ -609,9 +659,10 @@ __global__ __launch_bounds__(256) void k_bpotrf_panel(const BatchLP* __restrict_
   if (!go[lp] || p >= P.m) return;
   const int below = P.m - p - min(NB, P.m - p);
   if ((int)blockIdx.x > (below + kPanelRows - 1) / kPanelRows) return;
+  __shared__ __attribute__((aligned(16))) double lds[panel_lds_doubles<kPanelTPW>()];
   potrf_panel_mfma<kPanelTPW>(P.m, P.m, Mpool + P.M_off, P.ldm, p, blockIdx.x,
                               diagpool + P.diag_off + (long)(p / NB) * NB * NB, fail + lp,
-                              minp_bits + lp);
+                              minp_bits + lp, lds);
 }
 
 // Batched diagonal blocks into M: LP = blockIdx.y, block blockIdx.x.
@@ -630,13 +681,20 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
                       double* diag) {
   for (int p = 0; p < mc; p += NB) {
     const int nbe = (mc - p) < NB ? (mc - p) : NB;
-    const int grid = 1 + cdiv(mr - p - nbe, kPanelRows);
-    hipLaunchKernelGGL(k_potrf_panel_f64, dim3(grid), dim3(256), 0, st, mr, mc, M, ld, p, diag,
-                       info);
-    if (p + NB < mc) {
-      launch_syrk_f64(st, mr - p - NB, NB, M + (long)(p + NB) * ld + p, ld, nullptr,
-                      M + (long)(p + NB) * ld + (p + NB), ld, true, 64, 1, nullptr);
+    const int npw_need = 1 + cdiv(mr - p - nbe, kPanelRows);
+    // the previous panel's update of the columns from p + NB on rides along
+    int ntiles = 0, per_xcd = 0;
+    if (p > 0 && mr - (p + NB) > 0) {
+      const int nt = cdiv(mr - (p + NB), 64);
+      ntiles = nt * (nt + 1) / 2;
+      per_xcd = cdiv(ntiles, 8);
     }
+    const int npw = ntiles ? cdiv(npw_need, 8) * 8 : npw_need;
+    hipLaunchKernelGGL(k_chol_step, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M, ld, p,
+                       diag, info, npw_need, npw, ntiles, per_xcd);
+    if (p + NB < mc)
+      hipLaunchKernelGGL(k_chol_col0, dim3(cdiv(mr - (p + NB), 64)), dim3(256), 0, st, mr, M, ld,
+                         p);
   }
   hipLaunchKernelGGL(k_diag_to_m<double>, dim3(cdiv(mc, NB)), dim3(256), 0, st, mc, M, ld, diag);
 }
