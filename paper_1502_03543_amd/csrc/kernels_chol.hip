@@ -326,6 +326,71 @@ __device__ __forceinline__ mf4 mm16(const double (&a)[4], double b, mf4 c) {
   return c;
 }
 
+// Step 1 of a block for NTL tiles of a wavefront's rows, starting at tile
+// `first` of own: R[t] = the block's columns c0 .. c0 + 15 of the tile minus
+// the contributions of columns 0 .. c0 - 1, transposed (R[t][v] holds column
+// lane / 16 + 4 v of row lane % 16).  The next K-step's operands are loaded
+// while the current one is on the matrix cores.
+template <int NTL>
+__device__ __forceinline__ void panel_ustep(const double* L, const double* own, int c0, int first,
+                                            int lane, mf4 (&R)[4]) {
+  const int li = lane & 15, lq = lane >> 4;
+  const double* rows = own + (16 * first + li) * LDQ;
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) R[t][v] = rows[16 * t * LDQ + c0 + lq + 4 * v];
+  const int nk = c0 / 4;
+  if (nk == 0) return;
+  mf4 acc[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) acc[t] = mf4{0.0, 0.0, 0.0, 0.0};
+  const double* arow = L + (c0 + (lane & 3)) * LDQ + lq;
+  double a[4], bv[NTL];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) a[cb] = arow[4 * cb * LDQ];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) bv[t] = rows[16 * t * LDQ + lq];
+  for (int kq = 0; kq < nk; ++kq) {
+    const int kn = 4 * min(kq + 1, nk - 1);
+    double an[4], bn[NTL];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) an[cb] = arow[4 * cb * LDQ + kn];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) bn[t] = rows[16 * t * LDQ + kn + lq];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) acc[t] = mm16(a, bv[t], acc[t]);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) a[cb] = an[cb];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) bv[t] = bn[t];
+  }
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) R[t] -= acc[t];
+}
+
+// Step 3 of a block: tiles T0 .. NTL - 1 (from tile `first` of own) times
+// the inverse of the sub-block's factor, stored as the block's columns.
+template <int NTL, int T0>
+__device__ __forceinline__ void panel_sstep(const double* LI, double* own, int c0, int first,
+                                            int lane, const mf4 (&R)[4]) {
+  const int li = lane & 15, lq = lane >> 4;
+  double ai[4][4];
+#pragma unroll
+  for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) ai[kq][cb] = LI[(4 * cb + (lane & 3)) * LIP + 4 * kq + lq];
+  double* rows = own + (16 * first + li) * LDQ + c0 + lq;
+#pragma unroll
+  for (int t = T0; t < NTL; ++t) {
+    mf4 x = mf4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) x = mm16(ai[kq], R[t][kq], x);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rows[16 * t * LDQ + 4 * v] = x[v];
+  }
+}
+
 // LDS of the panel routine (doubles)
 template <int TPW>
 constexpr int panel_lds_doubles() {
@@ -393,64 +458,26 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
   }
   __syncthreads();
 
-  // this wavefront's rows: NT tiles of 16 starting at own
-  const bool active = wv == 0 || solve;
+  // this wavefront's rows in 16-row tiles from own; wavefront 0 works on its
+  // tiles from the diagonal sub-block down (tile b in block b), so its tile
+  // count depends on b: each count is its own instantiation, which keeps
+  // every register index and every matrix-core group free of branches
   double* own = wv == 0 ? L : S + (wv - 1) * (16 * TPW) * LDQ;
-  constexpr int NT = 4 > TPW ? 4 : TPW;
-  const int ntiles = wv == 0 ? 4 : TPW;
 #pragma unroll 1
   for (int b = 0; b < NB / CB; ++b) {
     const int c0 = b * CB;
-    // wavefront 0 needs its tiles from the diagonal sub-block down
-    const int t0 = wv == 0 ? b : 0;
-    mf4 R[NT];
-    if (active) {
-      // the block's columns as staged, then minus the finished columns'
-      // contributions (operands of the next K-step loaded ahead)
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          R[t][v] = (t < ntiles) ? own[(16 * t + li) * LDQ + c0 + lq + 4 * v] : 0.0;
-      mf4 acc[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = mf4{0.0, 0.0, 0.0, 0.0};
-      const int nk = c0 / 4;
-      double a[4], bv[NT];
-      if (nk > 0) {
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) a[cb] = L[(c0 + 4 * cb + (lane & 3)) * LDQ + lq];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) bv[t] = own[(16 * (t < ntiles ? t : 0) + li) * LDQ + lq];
-      }
-      for (int kq = 0; kq < nk; ++kq) {
-        const int kn = min(kq + 1, nk - 1);
-        double an[4], bn[NT];
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) an[cb] = L[(c0 + 4 * cb + (lane & 3)) * LDQ + 4 * kn + lq];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) bn[t] = own[(16 * (t < ntiles ? t : 0) + li) * LDQ + 4 * kn + lq];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (t < ntiles && t >= t0) acc[t] = mm16(a, bv[t], acc[t]);
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) a[cb] = an[cb];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) bv[t] = bn[t];
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) R[t] -= acc[t];
-    }
-
+    mf4 R[4];
     if (wv == 0) {
-      // the sub-block (tile b) to one row per lane, upper part zeroed; lanes
+      switch (b) {
+        case 0: panel_ustep<4>(L, own, c0, 0, lane, R); break;
+        case 1: panel_ustep<3>(L, own, c0, 1, lane, R); break;
+        case 2: panel_ustep<2>(L, own, c0, 2, lane, R); break;
+        default: panel_ustep<1>(L, own, c0, 3, lane, R); break;
+      }
+      // the sub-block (R[0]) to one row per lane, upper part zeroed; lanes
       // 16..31 start from the identity rows, lanes 32..63 from zero
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t == b) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) Y[li * YP + lq + 4 * v] = R[t][v];
-        }
+      for (int v = 0; v < 4; ++v) Y[li * YP + lq + 4 * v] = R[0][v];
       __builtin_amdgcn_wave_barrier();
       double y[CB];
 #pragma unroll
@@ -506,25 +533,19 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
 #pragma unroll
         for (int c = 0; c < CB; ++c) LI[c * LIP + lane - 16] = y[c];
       }
+    } else if (solve) {
+      panel_ustep<TPW>(L, own, c0, 0, lane, R);
     }
     __syncthreads();
-
-    if (active) {
-      double ai[4][4];
-#pragma unroll
-      for (int kq = 0; kq < 4; ++kq)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) ai[kq][cb] = LI[(4 * cb + (lane & 3)) * LIP + 4 * kq + lq];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        if (t < ntiles && (wv != 0 || t > b)) {
-          mf4 x = mf4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int kq = 0; kq < 4; ++kq) x = mm16(ai[kq], R[t][kq], x);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) own[(16 * t + li) * LDQ + c0 + lq + 4 * v] = x[v];
-        }
+    if (wv == 0) {
+      switch (b) {
+        case 0: panel_sstep<4, 1>(LI, own, c0, 0, lane, R); break;
+        case 1: panel_sstep<3, 1>(LI, own, c0, 1, lane, R); break;
+        case 2: panel_sstep<2, 1>(LI, own, c0, 2, lane, R); break;
+        default: break;
       }
+    } else if (solve) {
+      panel_sstep<TPW, 0>(LI, own, c0, 0, lane, R);
     }
     __syncthreads();
   }
