@@ -329,9 +329,8 @@ __device__ __forceinline__ mf4 mm16(const double (&a)[4], double b, mf4 c) {
 // Step 1 of a block for NTL tiles of a wavefront's rows, starting at tile
 // `first` of own: R[t] = the block's columns c0 .. c0 + 15 of the tile minus
 // the contributions of columns 0 .. c0 - 1, transposed (R[t][v] holds column
-// lane / 16 + 4 v of row lane % 16).  The next K-step's operands are loaded
-// while the current one is on the matrix cores.
-template <int NTL>
+// lane / 16 + 4 v of row lane % 16).
+template <int NTL, int NK>
 __device__ __forceinline__ void panel_ustep(const double* L, const double* own, int c0, int first,
                                             int lane, mf4 (&R)[4]) {
   const int li = lane & 15, lq = lane >> 4;
@@ -340,30 +339,20 @@ __device__ __forceinline__ void panel_ustep(const double* L, const double* own, 
   for (int t = 0; t < NTL; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) R[t][v] = rows[16 * t * LDQ + c0 + lq + 4 * v];
-  const int nk = c0 / 4;
-  if (nk == 0) return;
+  if (NK == 0) return;
+  // NK = c0 / 4 K-steps, fully unrolled: every operand load can be issued
+  // ahead of the matrix work that needs it
   mf4 acc[NTL];
 #pragma unroll
   for (int t = 0; t < NTL; ++t) acc[t] = mf4{0.0, 0.0, 0.0, 0.0};
   const double* arow = L + (c0 + (lane & 3)) * LDQ + lq;
-  double a[4], bv[NTL];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) a[cb] = arow[4 * cb * LDQ];
+  for (int kq = 0; kq < NK; ++kq) {
+    double a[4];
 #pragma unroll
-  for (int t = 0; t < NTL; ++t) bv[t] = rows[16 * t * LDQ + lq];
-  for (int kq = 0; kq < nk; ++kq) {
-    const int kn = 4 * min(kq + 1, nk - 1);
-    double an[4], bn[NTL];
+    for (int cb = 0; cb < 4; ++cb) a[cb] = arow[4 * cb * LDQ + 4 * kq];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) an[cb] = arow[4 * cb * LDQ + kn];
-#pragma unroll
-    for (int t = 0; t < NTL; ++t) bn[t] = rows[16 * t * LDQ + kn + lq];
-#pragma unroll
-    for (int t = 0; t < NTL; ++t) acc[t] = mm16(a, bv[t], acc[t]);
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) a[cb] = an[cb];
-#pragma unroll
-    for (int t = 0; t < NTL; ++t) bv[t] = bn[t];
+    for (int t = 0; t < NTL; ++t) acc[t] = mm16(a, rows[16 * t * LDQ + 4 * kq + lq], acc[t]);
   }
 #pragma unroll
   for (int t = 0; t < NTL; ++t) R[t] -= acc[t];
@@ -469,10 +458,10 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
     mf4 R[4];
     if (wv == 0) {
       switch (b) {
-        case 0: panel_ustep<4>(L, own, c0, 0, lane, R); break;
-        case 1: panel_ustep<3>(L, own, c0, 1, lane, R); break;
-        case 2: panel_ustep<2>(L, own, c0, 2, lane, R); break;
-        default: panel_ustep<1>(L, own, c0, 3, lane, R); break;
+        case 0: panel_ustep<4, 0>(L, own, c0, 0, lane, R); break;
+        case 1: panel_ustep<3, 4>(L, own, c0, 1, lane, R); break;
+        case 2: panel_ustep<2, 8>(L, own, c0, 2, lane, R); break;
+        default: panel_ustep<1, 12>(L, own, c0, 3, lane, R); break;
       }
       // the sub-block (R[0]) to one row per lane, upper part zeroed; lanes
       // 16..31 start from the identity rows, lanes 32..63 from zero
@@ -534,7 +523,12 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
         for (int c = 0; c < CB; ++c) LI[c * LIP + lane - 16] = y[c];
       }
     } else if (solve) {
-      panel_ustep<TPW>(L, own, c0, 0, lane, R);
+      switch (b) {
+        case 0: panel_ustep<TPW, 0>(L, own, c0, 0, lane, R); break;
+        case 1: panel_ustep<TPW, 4>(L, own, c0, 0, lane, R); break;
+        case 2: panel_ustep<TPW, 8>(L, own, c0, 0, lane, R); break;
+        default: panel_ustep<TPW, 12>(L, own, c0, 0, lane, R); break;
+      }
     }
     __syncthreads();
     if (wv == 0) {
