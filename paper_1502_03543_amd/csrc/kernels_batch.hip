@@ -292,10 +292,13 @@ __global__ __launch_bounds__(256) void k_btrsv(BatchArgs a, int k, int* err) {
 
 // g = A^T dy, g_y = A^T y, ds = r_d - g, dx = -x - d o ds, psi and its first
 // maximiser (x block before s block); zero and non-finite directions.
+constexpr int kDirStage = 1024;  // dy and y entries staged in LDS per LP
+
 __global__ __launch_bounds__(256) void k_bdir(BatchArgs a, int k, int* err) {
   __shared__ double shv[4];
   __shared__ long long shi[4];
   __shared__ int s_flag, s_cur;
+  __shared__ double sdy[kDirStage], sy[kDirStage];
   const int lp = blockIdx.x;
   if (!a.go[lp]) return;
   const int tid = threadIdx.x;
@@ -312,10 +315,35 @@ __global__ __launch_bounds__(256) void k_bdir(BatchArgs a, int k, int* err) {
   double best = -INFINITY;
   long long bi = LLONG_MAX;
   int nz = 0, nf = 0;
+  const int ms = min(m, kDirStage);
+  for (int i = tid; i < ms; i += 256) {
+    sdy[i] = V.dy[i];
+    sy[i] = y[i];
+  }
+  __syncthreads();
   for (int j = tid; j < n; j += 256) {
+    // sums in row order as before; the column's A entries are loaded eight
+    // rows ahead so the loads overlap instead of following one another
     double g1 = 0.0, g2 = 0.0;
-    for (int i = 0; i < m; ++i) {
-      const double av = V.A[(long)i * n + j];
+    const double* acol = V.A + j;
+    int i = 0;
+    for (; i + 8 <= ms; i += 8) {
+      double av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) av[u] = acol[(long)(i + u) * n];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        g1 += av[u] * sdy[i + u];
+        g2 += av[u] * sy[i + u];
+      }
+    }
+    for (; i < ms; ++i) {
+      const double av = acol[(long)i * n];
+      g1 += av * sdy[i];
+      g2 += av * sy[i];
+    }
+    for (; i < m; ++i) {
+      const double av = acol[(long)i * n];
       g1 += av * V.dy[i];
       g2 += av * y[i];
     }
