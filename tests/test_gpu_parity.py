@@ -55,7 +55,7 @@ def test_normal_matrix(torch_dev, m, n):
     assert np.all(Mg[~low] == 0.0)  # upper triangle untouched
 
 
-@pytest.mark.parametrize("m", [1, 64, 100, 200, 333])
+@pytest.mark.parametrize("m", [1, 64, 100, 200, 333, 700])
 def test_cholesky_and_solve(torch_dev, m):
     torch, dev = torch_dev
     from paper_1502_03543_amd import solver
