@@ -146,8 +146,10 @@ def mixed_compare():
     T = [torch.from_numpy(v).to(dev) for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
     del lp
     out = {"workload": "single LP m=8192 n=32768, Gaussian A, alpha 0.95, to gap 1e-8"}
-    for prec in ("mixed", "fp64"):
-        h = solver.LP(*T, alpha=0.95, precision=prec, profile=True)
+    runs = (("mixed", "mixed", {}), ("mixed_refine12", "mixed", {"refine_max": 12}),
+            ("fp64", "fp64", {}))
+    for name, prec, extra in runs:
+        h = solver.LP(*T, alpha=0.95, precision=prec, profile=True, **extra)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = h.solve(1e-8, 300, want_log=True)
@@ -155,7 +157,7 @@ def mixed_compare():
         dt = time.perf_counter() - t0
         tim = h.timings()
         log = r.get("log") or []
-        out[prec] = {
+        out[name] = {
             "status": capi.status_string(r["status"]), "iterations": r["iters"] + 1,
             "seconds": dt, "dual_obj": r["dual_obj"],
             "fp32_iterations": sum(1 for e in log if e["precision_used"] == capi.LP_PREC_MIXED),
@@ -165,8 +167,9 @@ def mixed_compare():
             "cholesky_ms_per_iteration": tim["potrf_ms"] / max(tim["iterations"], 1),
         }
         h.close()
-        print(json.dumps({prec: out[prec]}), flush=True)
+        print(json.dumps({name: out[name]}), flush=True)
     out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    out["speedup_mixed_refine12_vs_fp64"] = out["fp64"]["seconds"] / out["mixed_refine12"]["seconds"]
     out["dual_obj_rel_diff"] = abs(out["mixed"]["dual_obj"] - out["fp64"]["dual_obj"]) / max(
         1.0, abs(out["fp64"]["dual_obj"]))
     print(json.dumps(out))
