@@ -2,25 +2,19 @@
 // names Cholesky as the usual solver for the symmetric positive definite
 // A D A^T).  Row-major lower storage, panel width kTB = 64.
 //
-// Per panel p:
-//   1. k_potrf_panel: wavefront 0 of every workgroup factors the 64 x 64
-//      diagonal block (identical arithmetic in each, so identical results),
-//      one row per lane with the whole row in registers.  Step j broadcasts
-//      column j through LDS; the next pivot is taken straight from lane j+1
-//      with two readlanes, so its reciprocal square root overlaps the step's
-//      updates.  Every step is a template instance, so all register indices
-//      are compile-time constants.  Meanwhile wavefronts 1..3 stage 192 panel
-//      rows in LDS; after one barrier each of their lanes solves one row of
-//      L21 = M21 L11^-T by forward substitution.  Workgroup 0 stores L11.
-//   2. trailing update M22 -= L21 L21^T on the matrix cores (the normal-matrix
-//      kernel in subtract mode, lower tiles only).
-// Rows below the last column (mr > mc) are carried through both steps like
+// FP64, per panel p:
+//   1. k_chol_step: the panel step (potrf_panel_mfma: A11 and the panel rows
+//      on the matrix cores, L11 to a side buffer, the rows below solved in
+//      place) in its first workgroups and, in the others, the previous
+//      panel's update of the trailing columns from p + 64 on;
+//   2. k_chol_col0: panel p applied to the next panel's 64 columns.
+// FP32 (mixed precision): potrf_panel_body, one wavefront factoring A11 with
+// the panel rows solved by the other three, then the FP32 trailing update.
+// Rows below the last column (mr > mc) are carried through every step like
 // any other row: a right-hand side stored as row m comes out as (L^-1 r)^T,
 // so the forward triangular solve costs no launch of its own.
-// The pivot reciprocal square root is the hardware estimate refined by Newton
-// steps (within an ulp or two of the correctly rounded value).  A pivot that
-// is not a finite positive number is recorded (first column) in the
-// iteration info and turns the step into a breakdown; no fallback.
+// A pivot that is not a finite positive number is recorded (first column) in
+// the iteration info and turns the step into a breakdown; no fallback.
 #include <climits>
 #include <cmath>
 #include <utility>

@@ -1,31 +1,16 @@
-// Normal matrix M = A D A^T of the Section 5 normal equations, on the FP64
-// matrix cores of gfx950, and the same kernel in subtract mode for the
-// Cholesky trailing update (C -= L21 L21^T).
+// Normal matrix M = A D A^T of the Section 5 normal equations on the FP64
+// matrix cores of gfx950, and the same tile routine (syrk_tile.h) in
+// subtract mode for the Cholesky trailing update.
 //
-// Instruction: v_mfma_f64_4x4x4_4b (four independent 4x4x4 products per
-// wavefront; it sustains close to the FP64 matrix peak on gfx950, unlike the
-// 16x16x4 form).  Lane l = x + 4*blk + 16*y holds
-//   A operand: rowop[i = x][k = y] of block blk,
-//   B operand: colop[j = x][k = y] of block blk,
-//   D result : C[i = y][j = x] of block blk.
-// A wavefront register-blocks a (4R) x (16Q) output: the A operand carries 4
-// rows (identical across the 4 blocks), the B operand 16 columns (4 per
-// block), so each instruction produces a 4 x 16 slab for K = 4.
-//
-// Workgroup: 256 threads = 2 x 2 wavefronts; tile BM = 8R rows by BN = 32Q
-// columns (square).  Only tiles on or below the diagonal are launched.  Both
-// operands stream through double-buffered LDS in stages of KC along K, row by
-// row with a padded row length of KC + 4 doubles: a stage is written with
-// 16-byte stores that spread evenly over the 64 banks, the A operand read
-// (4 rows x 4 k, broadcast over the blocks) touches 16 distinct banks pairs
-// and the B read (16 rows x 4 k) needs the two passes its 512 bytes take
-// anyway.  (A blocked layout of 4 k by 16 rows made every stage write a
-// 16-way bank conflict.)  Global loads for the next stage are issued before the MFMA
-// work of the current one and consumed only when they are stored to LDS, so
-// they stay in flight during the matrix work.  The diagonal weight d is
-// applied to the row operand while it is staged.  Split-K writes per-split
-// partial tiles; the last split of a tile to finish (an arrival counter per
-// tile) sums them in split order, so results do not depend on scheduling.
+// Two FP64 families:
+//   * k_syrk_sk (below): stream-K over 128 x 128 lower tiles on
+//     v_mfma_f64_16x16x4f64, the choice for large shapes;
+//   * k_syrk_f64: split-K over 64 or 128 lower tiles with the four-block
+//     v_mfma_f64_4x4x4f64 tile routine of syrk_tile.h (small shapes, the
+//     batched normal matrices and the Cholesky updates).
+// Split-K writes per-split partial tiles; the last split of a tile to finish
+// (an arrival counter per tile) sums them in split order, so results do not
+// depend on scheduling.  The FP32 kernel (mixed precision) is further down.
 #include <cmath>
 
 #include "pdas_internal.h"

@@ -1,5 +1,24 @@
 // Normal-matrix / trailing-update tile routine shared by the normal-matrix
 // kernels and the fused Cholesky step (device code, included by both).
+//
+// Instruction: v_mfma_f64_4x4x4_4b (four independent 4x4x4 products per
+// wavefront).  Lane l = x + 4*blk + 16*y holds
+//   A operand: rowop[i = x][k = y] of block blk,
+//   B operand: colop[j = x][k = y] of block blk,
+//   D result : C[i = y][j = x] of block blk.
+// A wavefront register-blocks a (4R) x (16Q) output: the A operand carries 4
+// rows (identical across the 4 blocks), the B operand 16 columns (4 per
+// block), so each instruction produces a 4 x 16 slab for K = 4.
+//
+// Workgroup: 256 threads = 2 x 2 wavefronts; tile BM = 8R rows by BN = 32Q
+// columns (square).  Only tiles on or below the diagonal are launched.  Both
+// operands stream through double-buffered LDS in stages of KC along K, row by
+// row with a padded row length of KC + 4 doubles and 16-byte stage stores
+// (a blocked layout of 4 k by 16 rows made every stage write a 16-way bank
+// conflict).  Global loads for the next stage are issued before the MFMA
+// work of the current one and consumed only when they are stored to LDS, so
+// they stay in flight during the matrix work.  The diagonal weight d is
+// applied to the row operand while it is staged.
 #pragma once
 
 #include "pdas_internal.h"
