@@ -50,8 +50,16 @@ def potrf_flops(m: int) -> float:
 
 
 def source_digest() -> str:
-    p = os.path.join(ROOT, "paper_1502_03543_amd", "csrc", "kernels_syrk.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Digest of the normal-matrix kernel sources with comments and blank
+    lines dropped (a comment edit does not invalidate measured counters)."""
+    h = hashlib.sha256()
+    for name in ("kernels_syrk.hip", "syrk_tile.h"):
+        p = os.path.join(ROOT, "paper_1502_03543_amd", "csrc", name)
+        for line in open(p):
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
 
 
 def read_traffic(m: int, n: int):
@@ -64,7 +72,7 @@ def read_traffic(m: int, n: int):
         t = json.load(open(p))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != source_digest() or t.get("m") != m or t.get("n") != n:
+    if t.get("kernel_source_digest") != source_digest() or t.get("m") != m or t.get("n") != n:
         return None
     return t.get("bytes_per_launch")
 
