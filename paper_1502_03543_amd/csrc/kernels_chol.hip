@@ -536,6 +536,14 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
       panel_sstep<TPW, 0>(LI, own, c0, 0, lane, R);
     }
     __syncthreads();
+    // the block's 16 finished columns of the panel rows go out now, so the
+    // stores overlap the later blocks
+    if (solve) {
+      for (int e = tid; e < RW * CB; e += 256) {
+        const int row = e / CB, k = c0 + e % CB;
+        if (r0 + row < mr && k < nbe) M[(r0 + row) * ld + p + k] = S[row * LDQ + k];
+      }
+    }
   }
 
   if (wv == 0 && wg == 0) {
@@ -565,10 +573,6 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
       if (r < nbe && k <= r) diag_blk[e] = L[r * LDQ + k];
     }
     return;
-  }
-  for (int e = tid; e < RW * NB; e += 256) {
-    const int row = e / NB, k = e % NB;
-    if (r0 + row < mr && k < nbe) M[(r0 + row) * ld + p + k] = S[row * LDQ + k];
   }
 }
 
