@@ -137,6 +137,8 @@ def batch_variant(lpgen, solver, capi, torch, sample: int = 32) -> dict:
         "lp_by_lp_sample": f"single-LP solver on LPs 0..{sample - 1}, one after another",
         "speedup_vs_lp_by_lp": (len(lps) / tb) / (sample / ts),
         "status_counts": {k: names.count(k) for k in sorted(set(names))},
+        "iterations": {"max": int(np.max(res["iters"])), "mean": float(np.mean(res["iters"])),
+                       "p90": float(np.percentile(res["iters"], 90))},
     }
 
 

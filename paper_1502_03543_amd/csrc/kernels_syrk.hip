@@ -340,14 +340,18 @@ __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, lo
 __global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __restrict__ X,
                                                  long ldx, const double* __restrict__ w,
                                                  double* __restrict__ C, long ldc, int ntiles,
-                                                 double* __restrict__ part) {
-  constexpr int BM = kSkBM, G = kSkGroups;
+                                                 int G, double* __restrict__ part) {
+  // G <= kSkGroups workgroups, at most one per unit of work, so that every
+  // range is non-empty (a tile's counter expects one arrival per range that
+  // meets it); the XCD remap needs G to be a multiple of 8
+  constexpr int BM = kSkBM;
   const int S = (K + kSkKC - 1) / kSkKC;
   const long W = (long)ntiles * S;
-  const int g = (int)((blockIdx.x & 7) * (G / 8) + (blockIdx.x >> 3));
+  const int g = (G % 8 == 0) ? (int)((blockIdx.x & 7) * (G / 8) + (blockIdx.x >> 3))
+                             : (int)blockIdx.x;
   auto bnd = [&](long gg) { return gg * W / G; };
   const long b0 = bnd(g), b1 = bnd(g + 1);
-  int* cnt = reinterpret_cast<int*>(part + (long)G * 2 * BM * BM);
+  int* cnt = reinterpret_cast<int*>(part + (long)kSkGroups * 2 * BM * BM);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr0 = (wv >> 1) * (16 * kSkT), wc0 = (wv & 1) * (16 * kSkT);
@@ -510,8 +514,11 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
       launch_fill_i32(st, reinterpret_cast<int*>(part + (size_t)kSkGroups * 2 * kSkBM * kSkBM), 0,
                       ntiles);
       if (ev_begin) (void)hipEventRecord(ev_begin, st);
-      hipLaunchKernelGGL(k_syrk_sk, dim3(kSkGroups), dim3(256), 0, st, mm, K, X, ldx, w, C, ldc,
-                         ntiles, part);
+      const long work = (long)ntiles * cdiv(K, kSkKC);
+      int G = kSkGroups;
+      if (work < G) G = work >= 8 ? (int)(work / 8 * 8) : (int)work;
+      hipLaunchKernelGGL(k_syrk_sk, dim3(G), dim3(256), 0, st, mm, K, X, ldx, w, C, ldc, ntiles,
+                         G, part);
       if (ev_end) (void)hipEventRecord(ev_end, st);
       return;
     }

@@ -51,7 +51,8 @@ def test_emulated_cholesky_with_fused_forward_solve(emu, m):
 
 @pytest.mark.parametrize("m,n,tile,splits", [(150, 301, 128, 3), (200, 333, 64, 4),
                                              (130, 257, 128, 1), (70, 190, 64, 2),
-                                             (150, 302, 0, 0), (260, 98, 0, 0)])
+                                             (150, 302, 0, 0), (260, 98, 0, 0),
+                                             (100, 40, 0, 0)])
 def test_emulated_normal_matrix(emu, m, n, tile, splits):
     r = json.loads(_run(emu, "syrk", m, n, tile, splits).strip().splitlines()[-1])
     assert r["rel_err"] <= 1e-14, r
