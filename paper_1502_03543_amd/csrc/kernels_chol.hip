@@ -70,6 +70,10 @@ __device__ inline int opaque_zero() {
   return z;
 }
 
+// Marks v as live in a vector register here (emits nothing): the load that
+// produced it cannot be sunk below this point into a lane-dependent branch.
+__device__ inline void pin_vgpr(double& v) { asm volatile("" : "+v"(v)); }
+
 // Workgroup wg of the panel step at column p of an mr x mc lower matrix
 // (mr >= mc; rows beyond mc are extra right-hand sides stored as rows, whose
 // factor rows come out as L^-1 applied to them): every workgroup factors A11
@@ -362,7 +366,7 @@ __device__ __forceinline__ void panel_sstep(const double* LI, double* own, int c
 #pragma unroll
   for (int kq = 0; kq < 4; ++kq)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) ai[kq][cb] = LI[(4 * cb + (lane & 3)) * LIP + 4 * kq + lq];
+    for (int cb = 0; cb < 4; ++cb) ai[kq][cb] = LI[(4 * kq + lq) * LIP + 4 * cb + (lane & 3)];
   double* rows = own + (16 * first + li) * LDQ + c0 + lq;
 #pragma unroll
   for (int t = T0; t < NTL; ++t) {
@@ -377,7 +381,7 @@ __device__ __forceinline__ void panel_sstep(const double* LI, double* own, int c
 // LDS of the panel routine (doubles)
 template <int TPW>
 constexpr int panel_lds_doubles() {
-  return NB * LDQ + PanelShape<TPW>::rows * LDQ + CB * YP + CB * LIP + 2 * CB + NB;
+  return NB * LDQ + PanelShape<TPW>::rows * LDQ + CB * YP + CB * LIP + 2 * 64 + NB + CB;
 }
 
 template <int TPW>
@@ -389,9 +393,9 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
   double* L = lds;                       // A11 on entry, L11 (row-major, lower) at the end
   double* S = L + NB * LDQ;              // staged panel rows of this workgroup
   double* Y = S + RW * LDQ;              // diagonal sub-block, one row per lane
-  double* LI = Y + CB * YP;              // LI[c][q] = (L_bb^-1)[c][q]
-  double(*CL)[CB] = reinterpret_cast<double(*)[CB]>(LI + CB * LIP);  // multipliers of a step
-  double* PV = LI + CB * LIP + 2 * CB;   // pivots, checked after the last block
+  double* LI = Y + CB * YP;              // LI[q][c] = (L_bb^-1)[c][q]
+  double(*CL)[64] = reinterpret_cast<double(*)[64]>(LI + CB * LIP);  // multipliers of a step
+  double* PV = LI + CB * LIP + 2 * 64;   // pivots (+ CB unused), checked after the last block
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int nbe = min(NB, mc - p);
@@ -458,16 +462,27 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
         default: panel_ustep<1, 12>(L, own, c0, 3, lane, R); break;
       }
       // the sub-block (R[0]) to one row per lane, upper part zeroed; lanes
-      // 16..31 start from the identity rows, lanes 32..63 from zero
+      // 16..31 start from the identity rows; lanes 32..63 repeat lanes
+      // 0..31 (same rows, same steps, same values), so that every lane has
+      // something to store at the end and no store needs a branch
 #pragma unroll
       for (int v = 0; v < 4; ++v) Y[li * YP + lq + 4 * v] = R[0][v];
       __builtin_amdgcn_wave_barrier();
+      // all 16 reads are issued by every lane before any select (pinned, so
+      // the compiler cannot sink each read into a branch of its own, which
+      // costs one full LDS round trip per column)
+      const int lh = lane & 31;
       double y[CB];
 #pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        const double yv = Y[li * YP + c];
-        y[c] = lane < 16 ? (c <= lane ? yv : 0.0) : (lane - 16 == c ? 1.0 : 0.0);
-      }
+      for (int c = 0; c < CB; ++c) y[c] = Y[li * YP + c];
+      double d = Y[li * YP + li];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) pin_vgpr(y[c]);
+      pin_vgpr(d);
+      d = lh < 16 ? d : 0.0;
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        y[c] = lh < 16 ? (c <= lh ? y[c] : 0.0) : (lh - 16 == c ? 1.0 : 0.0);
       __builtin_amdgcn_wave_barrier();
       // step jj scales the pivot's column by the pivot's reciprocal square
       // root and takes it out of the later columns.  The pivot chain runs on
@@ -475,18 +490,25 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
       // handed over with one readlane), so only the off-diagonal updates need
       // the other rows' multipliers: they are broadcast through LDS and
       // applied one step late, filling the latency of the next pivot's
-      // reciprocal square root.
-      double d = lane < 16 ? Y[li * YP + li] : 0.0;
+      // reciprocal square root.  No lane-dependent branch inside the steps
+      // or in the stores after them (every lane stores its multiplier, lanes
+      // from 16 into slots nobody reads; lane jj keeps pivot jj by a
+      // select), so the 16 steps form one straight-line block the scheduler
+      // can interleave.
       double piv = RL<double>::rd(d, 0);
       double rinv = rsq_f64(piv);
-      double lprev = 0.0, clp[CB], cln[CB];
+      // lane index re-read per block: the 16 comparisons of the pivot
+      // selects stay inside the block (hoisted, their masks would not fit
+      // the scalar registers)
+      const int li_b = li + opaque_zero();
+      double mypiv = 0.0, lprev = 0.0, clp[CB], cln[CB];
 #pragma unroll
       for (int kk = 0; kk < CB; ++kk) clp[kk] = cln[kk] = 0.0;
 #pragma unroll
       for (int jj = 0; jj < CB; ++jj) {
         const double lij = y[jj] * rinv;
         y[jj] = lij;
-        if (lane == 0) PV[c0 + jj] = piv;
+        mypiv = li_b == jj ? d : mypiv;  // lane jj's d before step jj is pivot jj
         double rnext = 0.0;
         if (jj + 1 < CB) {
           d = fma(-lij, lij, d);
@@ -499,7 +521,7 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
           if (jj >= 1) y[kk] = fma(-lprev, clp[kk], y[kk]);
         if (jj + 1 < CB) {
           y[jj + 1] = fma(-lij, RL<double>::rd(lij, jj + 1), y[jj + 1]);
-          if (lane < 16) CL[jj & 1][lane] = lij;
+          CL[jj & 1][lane] = lij;
           __builtin_amdgcn_wave_barrier();
 #pragma unroll
           for (int kk = jj + 2; kk < CB; ++kk) cln[kk] = CL[jj & 1][kk];
@@ -509,13 +531,13 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
         for (int kk = 0; kk < CB; ++kk) clp[kk] = cln[kk];
         rinv = rnext;
       }
-      if (lane < 16) {
+      // rows of L11 (lanes 0..15) and columns of the inverse (lanes 16..31,
+      // stored as rows of LI), 16 consecutive doubles per lane; pivots of
+      // lanes 16..31 go to unused slots
+      double* dst = lh < 16 ? L + (c0 + li) * LDQ + c0 : LI + li * LIP;
 #pragma unroll
-        for (int c = 0; c < CB; ++c) L[(c0 + lane) * LDQ + c0 + c] = y[c];
-      } else if (lane < 32) {
-#pragma unroll
-        for (int c = 0; c < CB; ++c) LI[c * LIP + lane - 16] = y[c];
-      }
+      for (int c = 0; c < CB; ++c) dst[c] = y[c];
+      PV[(lh < 16 ? c0 : NB) + li] = mypiv;
     } else if (solve) {
       switch (b) {
         case 0: panel_ustep<TPW, 0>(L, own, c0, 0, lane, R); break;

@@ -1,8 +1,9 @@
 """Build the CPU emulation of the library's kernels (test infrastructure only).
 
 The HIP sources are compiled unchanged for the host with tests/emu/hip as the
-runtime, except for two textual substitutions: the one inline-asm register
-move (a compiler-opaque zero) becomes a plain zero, and the workspace carver
+runtime, except for three textual substitutions: the inline-asm register
+move of the compiler-opaque zero becomes a plain zero, the empty asm that pins
+a value in a vector register disappears, and the workspace carver
 of the batched solver gains poisoned guard zones between its pools, so that
 AddressSanitizer reports any kernel access that leaves its own pool.
 """
@@ -19,6 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 SOURCES = ["kernels_batch", "api_batch", "kernels_chol", "kernels_syrk"]
 
 ASM_ZERO = 'asm volatile("v_mov_b32 %0, 0" : "=v"(z));'
+ASM_PIN = 'asm volatile("" : "+v"(v));'
 CARVE_OLD = """    off = (off + kAlign - 1) / kAlign * kAlign;
     T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;"""
 CARVE_NEW = """    off = (off + kAlign - 1) / kAlign * kAlign;
@@ -50,6 +52,9 @@ def build() -> str:
             if ASM_ZERO not in text:
                 raise RuntimeError("kernels_chol.hip: opaque-zero asm not found")
             text = text.replace(ASM_ZERO, "z = 0;")
+            if ASM_PIN not in text:
+                raise RuntimeError("kernels_chol.hip: register-pin asm not found")
+            text = text.replace(ASM_PIN, "(void)v;")
         if name == "api_batch":
             if CARVE_OLD not in text:
                 raise RuntimeError("api_batch.hip: workspace carver not found")

@@ -56,10 +56,12 @@ static int run_chol(int m) {
   info.min_pivot = INFINITY;
   pdas::launch_potrf_f64(nullptr, m + 1, m, M.data(), ld, &info, diag.data());
   std::vector<long double> R((size_t)m * m, 0.0L);
+  long double minp = INFINITY;
   for (int j = 0; j < m; ++j)
     for (int i = j; i < m; ++i) {
       long double s = A[(size_t)i * ld + j];
       for (int k = 0; k < j; ++k) s -= R[(size_t)i * m + k] * R[(size_t)j * m + k];
+      if (i == j) minp = s < minp ? s : minp;
       R[(size_t)i * m + j] = (i == j) ? sqrtl(s) : s / R[(size_t)j * m + j];
     }
   double lerr = 0, lsc = 0, zerr = 0, zsc = 0;
@@ -76,8 +78,11 @@ static int run_chol(int m) {
     zerr = worse(zerr, std::fabs((double)(z[i] - M[(size_t)m * ld + i])));
     zsc = std::fmax(zsc, std::fabs((double)z[i]));
   }
-  printf("{\"m\": %d, \"fail\": %d, \"factor_rel_err\": %.3e, \"solve_rel_err\": %.3e}\n", m,
-         info.chol_fail == INT_MAX ? -1 : info.chol_fail, lerr / lsc, zerr / zsc);
+  const double perr = std::fabs((double)((info.min_pivot - minp) / minp));
+  printf("{\"m\": %d, \"fail\": %d, \"factor_rel_err\": %.3e, \"solve_rel_err\": %.3e, "
+         "\"min_pivot_rel_err\": %.3e}\n",
+         m, info.chol_fail == INT_MAX ? -1 : info.chol_fail, lerr / lsc, zerr / zsc,
+         std::isnan(perr) ? INFINITY : perr);
   return 0;
 }
 

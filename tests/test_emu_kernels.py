@@ -47,6 +47,7 @@ def test_emulated_cholesky_with_fused_forward_solve(emu, m):
     assert r["fail"] == -1
     assert r["factor_rel_err"] <= 1e-13, r
     assert r["solve_rel_err"] <= 1e-13, r
+    assert r["min_pivot_rel_err"] <= 1e-13, r
 
 
 @pytest.mark.parametrize("m,n,tile,splits", [(150, 301, 128, 3), (200, 333, 64, 4),
