@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1502_03543_amd", "csrc")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_batch", "api_batch", "kernels_chol", "kernels_syrk"]
+SOURCES = ["kernels_batch", "api_batch", "kernels_chol", "kernels_syrk", "kernels_trsv"]
 
 ASM_ZERO = 'asm volatile("v_mov_b32 %0, 0" : "=v"(z));'
 ASM_PIN = 'asm volatile("" : "+v"(v));'

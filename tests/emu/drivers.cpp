@@ -5,6 +5,9 @@
 //                                     against a long-double reference
 //   emu syrk <m> <n> <tile> <splits>  normal matrix (tile 0: stream-K), against a
 //                                     long-double reference
+//   emu trsv <m>                      L z = r and L^T y = z with a fixed
+//                                     lower-triangular L; prints both errors
+//                                     against long-double substitution
 //   emu batch <in> <out> <max_iter> <tape>
 //                                     batched solve of the LPs in <in>; with a
 //                                     tape, also the reverse sweep
@@ -108,6 +111,43 @@ static int run_syrk(int m, int n, int tile, int splits) {
   return 0;
 }
 
+static int run_trsv(int m) {
+  const long ld = m + 5;
+  const int nblk = (m + 63) / 64;
+  std::vector<double> L((size_t)m * ld, NAN), r(m), z(m, NAN), y(m, NAN);
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < i; ++j) L[(size_t)i * ld + j] = 0.3 * std::sin(0.37 * i + 1.1 * j) / (1.0 + 0.05 * (i - j));
+    L[(size_t)i * ld + i] = 1.5 + 0.5 * std::cos(0.9 * i);
+    r[i] = std::cos(0.21 * i + 0.4);
+  }
+  std::vector<int> sync(4 + 2 * nblk, 0);
+  pdas::DevInfo info{};
+  pdas::launch_trsv_fwd(nullptr, m, L.data(), ld, r.data(), z.data(), sync.data(), &info);
+  pdas::launch_trsv_bwd(nullptr, m, L.data(), ld, z.data(), y.data(), sync.data(), &info);
+  std::vector<long double> zr(m), yr(m);
+  for (int i = 0; i < m; ++i) {
+    long double v = r[i];
+    for (int k = 0; k < i; ++k) v -= (long double)L[(size_t)i * ld + k] * zr[k];
+    zr[i] = v / L[(size_t)i * ld + i];
+  }
+  // the backward solve is checked on the device's z, so its error is its own
+  for (int i = m - 1; i >= 0; --i) {
+    long double v = z[i];
+    for (int k = i + 1; k < m; ++k) v -= (long double)L[(size_t)k * ld + i] * yr[k];
+    yr[i] = v / L[(size_t)i * ld + i];
+  }
+  double ze = 0, zs = 0, ye = 0, ys = 0;
+  for (int i = 0; i < m; ++i) {
+    ze = worse(ze, std::fabs((double)(z[i] - zr[i])));
+    zs = std::fmax(zs, std::fabs((double)zr[i]));
+    ye = worse(ye, std::fabs((double)(y[i] - yr[i])));
+    ys = std::fmax(ys, std::fabs((double)yr[i]));
+  }
+  printf("{\"m\": %d, \"err_flag\": %d, \"fwd_rel_err\": %.3e, \"bwd_rel_err\": %.3e}\n", m,
+         info.trsv_err, ze / zs, ye / ys);
+  return 0;
+}
+
 static int run_batch(const char* in, const char* out, int max_iter, int tape) {
   FILE* f = fopen(in, "rb");
   if (!f) return 2;
@@ -185,6 +225,7 @@ int main(int argc, char** argv) {
   if (argc >= 3 && !strcmp(argv[1], "chol")) return run_chol(atoi(argv[2]));
   if (argc >= 6 && !strcmp(argv[1], "syrk"))
     return run_syrk(atoi(argv[2]), atoi(argv[3]), atoi(argv[4]), atoi(argv[5]));
+  if (argc >= 3 && !strcmp(argv[1], "trsv")) return run_trsv(atoi(argv[2]));
   if (argc >= 6 && !strcmp(argv[1], "batch"))
     return run_batch(argv[2], argv[3], atoi(argv[4]), atoi(argv[5]));
   fprintf(stderr, "usage: emu chol <m> | emu batch <in> <out> <max_iter> <tape>\n");

@@ -121,6 +121,16 @@ inline T __shfl(T v, int src, int width = 64) {
   return emu_exchange(v, base + (src & (width - 1)));
 }
 inline int __builtin_amdgcn_readlane(int v, int lane) { return emu_exchange(v, lane); }
+// wavefront vote: nonzero when the predicate holds in any lane
+inline int __any(int p) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  g_wave_buf[w][l] = p != 0;
+  g_wave_bar[w].wait();
+  int r = 0;
+  for (int i = 0; i < 64; ++i) r |= g_wave_buf[w][i] != 0;
+  g_wave_bar[w].wait();
+  return r;
+}
 // the written value is a scalar register on the hardware: the first lane's
 inline int __builtin_amdgcn_writelane(int v, int lane, int old) {
   const int u = emu_exchange(v, 0);

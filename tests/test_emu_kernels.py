@@ -59,6 +59,14 @@ def test_emulated_normal_matrix(emu, m, n, tile, splits):
     assert r["rel_err"] <= 1e-14, r
 
 
+@pytest.mark.parametrize("m", [1, 40, 64, 100, 200, 300])
+def test_emulated_triangular_solves(emu, m):
+    r = json.loads(_run(emu, "trsv", m).strip().splitlines()[-1])
+    assert r["err_flag"] == 0, r
+    assert r["fwd_rel_err"] <= 1e-13, r
+    assert r["bwd_rel_err"] <= 1e-13, r
+
+
 def _write(path, lps):
     with open(path, "wb") as f:
         f.write(struct.pack("i", len(lps)))
