@@ -234,11 +234,11 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restric
 // Stream-K normal matrix on v_mfma_f64_16x16x4f64 (lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; slot v of the result is
 // D[l / 16 + 4 v][l % 16]).  The 16x16 product has no replicated operand, so
-// a K-step of a wavefront's 64 x 64 block needs 8 LDS reads for 16
-// instructions (the 4x4x4 form needs 20 for the same work); that is what
+// a K-step of a wavefront's 64 x 32 block needs 6 LDS reads for 8
+// instructions (the 4x4x4 form needs 18 for the same work); that is what
 // keeps this kernel off the LDS bandwidth limit.
 //
-// Workgroup tile 128 x 128 (2 x 2 wavefronts of 64 x 64), stages of 32 along
+// Workgroup tile 128 x 128 (2 x 4 wavefronts of 64 x 32), stages of 32 along
 // K through double-buffered LDS rows padded to 34 doubles.  The iteration
 // space (lower tiles x stages, tile-major) is cut into kSkGroups equal
 // contiguous ranges, one per workgroup, so every compute unit gets the same
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restric
 // in registers, with lane-contiguous loads.  Consecutive workgroup ids land
 // on different XCDs; the range index is remapped so that each XCD owns one
 // contiguous eighth of the work.
-constexpr int kSkT = 4;                 // 16 x 16 blocks per wavefront side
+constexpr int kSkT = 4;                 // 16 x 16 blocks per wavefront, rows
 constexpr int kSkBM = 32 * kSkT;        // 128
 constexpr int kSkKC = 32;
 constexpr int kSkLS = kSkKC + 2;
@@ -259,12 +259,26 @@ constexpr int kSkGroups = 256;          // one workgroup per compute unit
 
 typedef double sk4 __attribute__((ext_vector_type(4)));
 
+// Wavefront grid of a workgroup: 2 x WC wavefronts, each a 64 x (128 / WC)
+// part of the tile (kSkT x TC blocks of 16 x 16).  With WC = 4 (eight
+// wavefronts, 222 registers each) two wavefronts share each SIMD, so one
+// wavefront's operand reads and barrier waits overlap the other's matrix
+// work; measured 9% faster than four wavefronts of 4 x 4 blocks.
+template <int WC>
+struct SkShape {
+  static constexpr int waves = 2 * WC, threads = 64 * waves;
+  static constexpr int TC = 8 / WC;  // 16 x 16 blocks per wavefront, columns
+};
+constexpr int kSkWC = 4;
+
 // Tile t over k in [kbeg, kend) into acc (the whole workgroup takes part).
+template <int WC>
 __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, long ldx,
                                         const double* __restrict__ w, int t, int kbeg, int kend,
-                                        sk4 (&acc)[kSkT][kSkT], bool active) {
+                                        sk4 (&acc)[kSkT][SkShape<WC>::TC], bool active) {
+  constexpr int NT = SkShape<WC>::threads, TC = SkShape<WC>::TC;
   constexpr int PPR = kSkKC / 2;
-  constexpr int PAIRS = kSkBM * PPR / 256;
+  constexpr int PAIRS = kSkBM * PPR / NT;
   __shared__ __attribute__((aligned(16))) double lds[2][2][kSkBM * kSkLS];
   int ti, tj;
   tile_coords(t, ti, tj);
@@ -272,13 +286,13 @@ __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, lo
   const int nst = (kend - kbeg + kSkKC - 1) / kSkKC;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr0 = (wv >> 1) * (16 * kSkT), wc0 = (wv & 1) * (16 * kSkT);
+  const int wr0 = (wv / WC) * (16 * kSkT), wc0 = (wv % WC) * (16 * TC);
   double2 pa[PAIRS], pb[PAIRS], pw[PAIRS];
   auto gload = [&](int st) {
     const int kb = kbeg + st * kSkKC;
 #pragma unroll
     for (int it = 0; it < PAIRS; ++it) {
-      const int p = tid + 256 * it;
+      const int p = tid + NT * it;
       const int row = p / PPR, k = kb + 2 * (p % PPR);
       const long ra = min(row0 + row, mm - 1), rb = min(col0 + row, mm - 1);
       const int kc = min(k, kend - 2);
@@ -291,7 +305,7 @@ __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, lo
     const int kb = kbeg + st * kSkKC;
 #pragma unroll
     for (int it = 0; it < PAIRS; ++it) {
-      const int p = tid + 256 * it;
+      const int p = tid + NT * it;
       const int row = p / PPR, kk = 2 * (p % PPR), k = kb + kk;
       const bool va = row0 + row < mm, vb = col0 + row < mm;
       const bool v0 = k < kend, v1 = k + 1 < kend;
@@ -317,15 +331,15 @@ __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, lo
       const double* lb = lds[cur][1];
 #pragma unroll
       for (int ks = 0; ks < kSkKC / 4; ++ks) {
-        double a[kSkT], b[kSkT];
+        double a[kSkT], b[TC];
 #pragma unroll
         for (int r = 0; r < kSkT; ++r) a[r] = la[(wr0 + 16 * r + li) * kSkLS + 4 * ks + lk];
 #pragma unroll
-        for (int c = 0; c < kSkT; ++c) b[c] = lb[(wc0 + 16 * c + li) * kSkLS + 4 * ks + lk];
+        for (int c = 0; c < TC; ++c) b[c] = lb[(wc0 + 16 * c + li) * kSkLS + 4 * ks + lk];
 #pragma unroll
         for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-          for (int c = 0; c < kSkT; ++c)
+          for (int c = 0; c < TC; ++c)
             acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
       }
     }
@@ -337,14 +351,14 @@ __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, lo
 // C (lower, ldc) = X diag(w) X^T; X rows 16-byte aligned, K even.
 // part: kSkGroups * 2 partial tiles, then one arrival counter per tile
 // (zero on entry; every counter is back at zero when the launch ends).
-__global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __restrict__ X,
-                                                 long ldx, const double* __restrict__ w,
-                                                 double* __restrict__ C, long ldc, int ntiles,
-                                                 int G, double* __restrict__ part) {
+template <int WC>
+__global__ __launch_bounds__(SkShape<WC>::threads) void k_syrk_sk(
+    int mm, int K, const double* __restrict__ X, long ldx, const double* __restrict__ w,
+    double* __restrict__ C, long ldc, int ntiles, int G, double* __restrict__ part) {
   // G <= kSkGroups workgroups, at most one per unit of work, so that every
   // range is non-empty (a tile's counter expects one arrival per range that
   // meets it); the XCD remap needs G to be a multiple of 8
-  constexpr int BM = kSkBM;
+  constexpr int BM = kSkBM, TC = SkShape<WC>::TC, NQ = kSkT * TC;
   const int S = (K + kSkKC - 1) / kSkKC;
   const long W = (long)ntiles * S;
   const int g = (G % 8 == 0) ? (int)((blockIdx.x & 7) * (G / 8) + (blockIdx.x >> 3))
@@ -354,7 +368,7 @@ __global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __
   int* cnt = reinterpret_cast<int*>(part + (long)kSkGroups * 2 * BM * BM);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr0 = (wv >> 1) * (16 * kSkT), wc0 = (wv & 1) * (16 * kSkT);
+  const int wr0 = (wv / WC) * (16 * kSkT), wc0 = (wv % WC) * (16 * TC);
   __shared__ int s_last;
   for (long it = b0; it < b1;) {
     const int t = (int)(it / S), s0 = (int)(it % S);
@@ -364,19 +378,19 @@ __global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __
     const int row0 = ti * BM, col0 = tj * BM;
     // wavefronts of a diagonal tile whose block lies above the diagonal idle
     const bool active = !(ti == tj && wr0 + 16 * kSkT <= wc0);
-    sk4 acc[kSkT][kSkT];
+    sk4 acc[kSkT][TC];
 #pragma unroll
     for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-      for (int c = 0; c < kSkT; ++c) acc[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
-    sk_tile(mm, X, ldx, w, t, s0 * kSkKC, min(K, s1 * kSkKC), acc, active);
+      for (int c = 0; c < TC; ++c) acc[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
+    sk_tile<WC>(mm, X, ldx, w, t, s0 * kSkKC, min(K, s1 * kSkKC), acc, active);
     const bool whole = (s0 == 0 && s1 == S);
     if (whole) {
       if (active) {
 #pragma unroll
         for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-          for (int c = 0; c < kSkT; ++c)
+          for (int c = 0; c < TC; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
@@ -385,15 +399,15 @@ __global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __
       }
     } else {
       // partial tile in register order (lane-contiguous, so both the store and
-      // the reducer's loads are coalesced): element (q = r kSkT + c, v) of
-      // lane l of wavefront wv at ((wv * 16 + q) * 64 + l) * 4 + v
+      // the reducer's loads are coalesced): element (q = r TC + c, v) of
+      // lane l of wavefront wv at ((wv * NQ + q) * 64 + l) * 4 + v
       double* P = part + ((long)g * 2 + (it == b0 ? 0 : 1)) * (BM * BM);
       if (active) {
 #pragma unroll
         for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-          for (int c = 0; c < kSkT; ++c)
-            *reinterpret_cast<sk4*>(P + ((wv * 16 + r * kSkT + c) * 64 + lane) * 4) = acc[r][c];
+          for (int c = 0; c < TC; ++c)
+            *reinterpret_cast<sk4*>(P + ((wv * NQ + r * TC + c) * 64 + lane) * 4) = acc[r][c];
       }
       // the workgroups whose ranges meet tile t
       const long xs = (long)t * S, xe = xs + S - 1;
@@ -403,7 +417,14 @@ __global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __
       while (bnd(ghi) > xe) --ghi;
       while (bnd(ghi + 1) <= xe) ++ghi;
       const int nseg = (int)(ghi - glo + 1);
-      __threadfence();
+      // One device-scope release / acquire per workgroup, by thread 0 (the
+      // counter update), not one per thread: each is a writeback (and
+      // invalidate) of the whole L2 of its XCD, which by then holds most
+      // of the partial tiles, and hundreds of them at the end of the
+      // launch cost more than the tile work.  Every wavefront first waits
+      // for its own partial stores; the barriers carry the ordering from
+      // and to the other wavefronts of the workgroup.
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (tid == 0) {
         const int prev = __hip_atomic_fetch_add(&cnt[t], 1, __ATOMIC_ACQ_REL,
@@ -413,40 +434,39 @@ __global__ __launch_bounds__(256) void k_syrk_sk(int mm, int K, const double* __
       }
       __syncthreads();
       if (s_last && active) {
-        __threadfence();
         // sum of the segments in workgroup order; this workgroup's own
         // segment is still in registers
-        sk4 tot[kSkT][kSkT];
+        sk4 tot[kSkT][TC];
 #pragma unroll
         for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-          for (int c = 0; c < kSkT; ++c) tot[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
+          for (int c = 0; c < TC; ++c) tot[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
         for (long gg = glo; gg <= ghi; ++gg) {
           if (gg == g) {
 #pragma unroll
             for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-              for (int c = 0; c < kSkT; ++c) tot[r][c] += acc[r][c];
+              for (int c = 0; c < TC; ++c) tot[r][c] += acc[r][c];
           } else {
             // slot 0 when tile t is where workgroup gg's range starts
             const int sl = (bnd(gg) / S == t) ? 0 : 1;
             const double* Q = part + (gg * 2 + sl) * (BM * BM);
-            sk4 pv[kSkT][kSkT];
+            sk4 pv[kSkT][TC];
 #pragma unroll
             for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-              for (int c = 0; c < kSkT; ++c)
-                pv[r][c] = *reinterpret_cast<const sk4*>(Q + ((wv * 16 + r * kSkT + c) * 64 + lane) * 4);
+              for (int c = 0; c < TC; ++c)
+                pv[r][c] = *reinterpret_cast<const sk4*>(Q + ((wv * NQ + r * TC + c) * 64 + lane) * 4);
 #pragma unroll
             for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-              for (int c = 0; c < kSkT; ++c) tot[r][c] += pv[r][c];
+              for (int c = 0; c < TC; ++c) tot[r][c] += pv[r][c];
           }
         }
 #pragma unroll
         for (int r = 0; r < kSkT; ++r)
 #pragma unroll
-          for (int c = 0; c < kSkT; ++c)
+          for (int c = 0; c < TC; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
@@ -517,8 +537,8 @@ void launch_syrk_f64(hipStream_t st, int mm, int K, const double* X, long ldx, c
       const long work = (long)ntiles * cdiv(K, kSkKC);
       int G = kSkGroups;
       if (work < G) G = work >= 8 ? (int)(work / 8 * 8) : (int)work;
-      hipLaunchKernelGGL(k_syrk_sk, dim3(G), dim3(256), 0, st, mm, K, X, ldx, w, C, ldc, ntiles,
-                         G, part);
+      hipLaunchKernelGGL(k_syrk_sk<kSkWC>, dim3(G), dim3(SkShape<kSkWC>::threads), 0, st, mm, K,
+                         X, ldx, w, C, ldc, ntiles, G, part);
       if (ev_end) (void)hipEventRecord(ev_end, st);
       return;
     }

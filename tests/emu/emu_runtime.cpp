@@ -12,9 +12,9 @@
 dim3 threadIdx;
 dim3 blockIdx, blockDim, gridDim;
 EmuBarrier g_block_bar;
-EmuBarrier g_wave_bar[4];
-uint64_t g_wave_buf[4][64];
-uint64_t g_wave_buf2[4][64];
+EmuBarrier g_wave_bar[kEmuWaves];
+uint64_t g_wave_buf[kEmuWaves][64];
+uint64_t g_wave_buf2[kEmuWaves][64];
 long g_barrier_count = 0;
 long g_progress = 0;
 
@@ -69,7 +69,11 @@ void emu_yield() {
 void emu_run_block(int nt, std::function<void()> body) {
   g_body = std::move(body);
   g_block_bar.init(nt, "block");
-  for (int w = 0; w < 4; ++w) g_wave_bar[w].init(64, "wave");
+  if (nt > 64 * kEmuWaves) {
+    fprintf(stderr, "EMU: %d threads per workgroup exceed %d\n", nt, 64 * kEmuWaves);
+    std::abort();
+  }
+  for (int w = 0; w < kEmuWaves; ++w) g_wave_bar[w].init(64, "wave");
   g_f.assign(nt, Fiber{});
   if (g_stacks.size() < (size_t)nt * kStack) g_stacks.resize((size_t)nt * kStack);
   EMU_UNPOISON(g_stacks.data(), g_stacks.size());

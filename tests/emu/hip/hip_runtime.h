@@ -62,9 +62,10 @@ struct EmuBarrier {
   void wait();
 };
 extern EmuBarrier g_block_bar;
-extern EmuBarrier g_wave_bar[4];
-extern uint64_t g_wave_buf[4][64];
-extern uint64_t g_wave_buf2[4][64];
+constexpr int kEmuWaves = 16;  // up to 1024 threads per workgroup
+extern EmuBarrier g_wave_bar[kEmuWaves];
+extern uint64_t g_wave_buf[kEmuWaves][64];
+extern uint64_t g_wave_buf2[kEmuWaves][64];
 extern long g_barrier_count;
 extern long g_progress;
 
@@ -89,6 +90,7 @@ inline void __threadfence() {}
 inline void __builtin_amdgcn_wave_barrier() { g_wave_bar[threadIdx.x >> 6].wait(); }
 inline void __builtin_amdgcn_sched_barrier(int) {}
 inline void __builtin_amdgcn_s_sleep(int) {}
+inline void __builtin_amdgcn_s_waitcnt(int) {}
 
 template <typename T>
 inline uint64_t emu_bits(T v) {
