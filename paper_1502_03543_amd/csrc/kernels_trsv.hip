@@ -38,11 +38,12 @@ __device__ inline double readlane_d(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Thread 0 waits until flag != 0; returns false when the solve is aborted.
+// Thread 0 waits until flag != 0 (relaxed polls; the acquire follows once,
+// in every thread); returns false when the solve is aborted.
 __device__ bool wait_flag(int* flag, DevInfo* info, int* s_abort) {
   if (threadIdx.x == 0) {
     int spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
       if (++spins > kSpinLimit ||
           __hip_atomic_load(&info->trsv_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         atomicOr(&info->trsv_err, 1);
@@ -59,8 +60,9 @@ __device__ bool wait_flag(int* flag, DevInfo* info, int* s_abort) {
   return true;
 }
 
+// The release store orders this wavefront's earlier stores (the solved
+// entries) before the flag.
 __device__ inline void publish(int* flag) {
-  __threadfence();
   __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -190,10 +190,14 @@ __device__ __forceinline__ void syrk_f64_tile(int mm, int K, const double* __res
         }
     }
     // The last split of this tile to arrive sums all partial tiles in split
-    // order (so the result does not depend on which one arrives last).
+    // order (so the result does not depend on which one arrives last).  The
+    // only device-scope release / acquire is thread 0's counter update (each
+    // one writes back / invalidates the XCD's whole L2): every wavefront
+    // waits for its own stores, and the barriers order the other
+    // wavefronts' accesses with it.
     __shared__ int s_last;
     int* cnt = reinterpret_cast<int*>(part + (long)nsplit * ntiles * (BM * BM));
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) {
       const int prev = __hip_atomic_fetch_add(&cnt[t], 1, __ATOMIC_ACQ_REL,
@@ -203,7 +207,6 @@ __device__ __forceinline__ void syrk_f64_tile(int mm, int K, const double* __res
     }
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     for (int e = tid; e < BM * BM; e += 256) {
       const int lr = e / BM, lc = e % BM;
       const int gr = row0 + lr, gc = col0 + lc;
