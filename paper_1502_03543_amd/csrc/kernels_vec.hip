@@ -135,6 +135,7 @@ __global__ __launch_bounds__(256) void k_gemv_n(long m, long n, const double* __
     const double2* a2 = reinterpret_cast<const double2*>(a);
     const double2* w2 = reinterpret_cast<const double2*>(w);
     const long n2 = n >> 1;
+#pragma unroll 8
     for (long j = lane; j < n2; j += 64) {
       const double2 av = a2[j], wv = w2[j];
       acc += av.x * wv.x;
@@ -166,7 +167,9 @@ __global__ __launch_bounds__(256) void k_gemv_t(long m, long n, const double* __
   if (j >= n) return;
   double a1 = 0, a2 = 0;
   const double* a = A + i0 * n + j;
+  // (unrolled: the row loads run ahead of the sequential accumulation)
   if (v2) {
+#pragma unroll 16
     for (long i = 0; i < i1 - i0; ++i) {
       const double av = a[i * n];
       a1 += av * sv1[i];
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(long m, long n, const double* __
     }
     P2[chunk * n + j] = a2;
   } else {
+#pragma unroll 16
     for (long i = 0; i < i1 - i0; ++i) a1 += a[i * n] * sv1[i];
   }
   P1[chunk * n + j] = a1;
@@ -201,9 +205,13 @@ __global__ __launch_bounds__(256) void k_dir(long n, const double* P1, const dou
   long long bi = LLONG_MAX;
   int nz = 0, nf = 0;
   if (j < n) {
+    // the chunk partials in chunk order; unrolled so that the loads are
+    // issued ahead of the (still sequential) additions
     double g = 0, gyv = 0;
+#pragma unroll 8
     for (int k = 0; k < nchunks; ++k) g += P1[(long)k * n + j];
     if (P2) {
+#pragma unroll 8
       for (int k = 0; k < nchunks; ++k) gyv += P2[(long)k * n + j];
       gy[j] = gyv;
     }
