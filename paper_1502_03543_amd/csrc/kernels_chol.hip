@@ -647,13 +647,19 @@ __global__ __launch_bounds__(256) void k_chol_step(int mr, int mc, double* __res
 }
 
 // Update of the next panel's columns p + NB .. p + 2 NB - 1 (all rows from
-// p + NB) with panel p: the first tile column of the trailing update.
+// p + NB) with panel p: the first two 32-wide tile columns of the trailing
+// update.  This update sits on the critical path between two panels, so it
+// uses 32 x 32 tiles: four times the workgroups of 64 x 64 tiles, each with
+// a quarter of the work.  Workgroup b takes tile (0, 0) for b = 0, else
+// ((b + 1) / 2, (b + 1) % 2).
+constexpr int kCol0BM = 32;
 __global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ M, long ld, int p) {
-  __shared__ double2 lds2[syrk_tile_lds2<8, 32>()];
-  const int q = p + NB, ti = blockIdx.x;
-  syrk_f64_tile<8, 2, 32, false, true>(mr - q, NB, M + (long)q * ld + p, ld, nullptr,
-                                       M + (long)q * ld + q, ld, 1, ti * (ti + 1) / 2, 0, 0, 1, NB,
-                                       nullptr, lds2);
+  __shared__ double2 lds2[syrk_tile_lds2<4, 32>()];
+  const int q = p + NB, b = blockIdx.x;
+  const int ti = (b + 1) / 2, tj = b == 0 ? 0 : (b + 1) % 2;
+  syrk_f64_tile<4, 1, 32, false, true>(mr - q, NB, M + (long)q * ld + p, ld, nullptr,
+                                       M + (long)q * ld + q, ld, 1, ti * (ti + 1) / 2 + tj, 0, 0,
+                                       1, NB, nullptr, lds2);
 }
 
 __global__ __launch_bounds__(256) void k_potrf_panel_f32(int mr, int mc, float* __restrict__ M,
@@ -728,8 +734,8 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
     hipLaunchKernelGGL(k_chol_step, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M, ld, p,
                        diag, info, npw_need, npw, ntiles, per_xcd);
     if (p + NB < mc)
-      hipLaunchKernelGGL(k_chol_col0, dim3(cdiv(mr - (p + NB), 64)), dim3(256), 0, st, mr, M, ld,
-                         p);
+      hipLaunchKernelGGL(k_chol_col0, dim3(2 * cdiv(mr - (p + NB), kCol0BM) - 1), dim3(256), 0, st,
+                         mr, M, ld, p);
   }
   hipLaunchKernelGGL(k_diag_to_m<double>, dim3(cdiv(mc, NB)), dim3(256), 0, st, mc, M, ld, diag);
 }
