@@ -558,10 +558,12 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
       panel_sstep<TPW, 0>(LI, own, c0, 0, lane, R);
     }
     __syncthreads();
-    // the block's 16 finished columns of the panel rows go out now, so the
-    // stores overlap the later blocks
-    if (solve) {
-      for (int e = tid; e < RW * CB; e += 256) {
+    // the block's 16 finished columns of the panel rows go out now, written
+    // by wavefronts 1..3 only: wavefront 0 goes straight on to the next
+    // block's sub-block and factor chain, the critical path, while the
+    // others have slack until the next barrier
+    if (solve && wv > 0) {
+      for (int e = tid - 64; e < RW * CB; e += 192) {
         const int row = e / CB, k = c0 + e % CB;
         if (r0 + row < mr && k < nbe) M[(r0 + row) * ld + p + k] = S[row * LDQ + k];
       }
