@@ -561,9 +561,12 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
     // the block's 16 finished columns of the panel rows go out now, written
     // by wavefronts 1..3 only: wavefront 0 goes straight on to the next
     // block's sub-block and factor chain, the critical path, while the
-    // others have slack until the next barrier
-    if (solve && wv > 0) {
-      for (int e = tid - 64; e < RW * CB; e += 192) {
+    // others have slack until the next barrier (after the last block all
+    // four share the stores)
+    const bool last = b == NB / CB - 1;
+    if (solve && (wv > 0 || last)) {
+      const int t0 = last ? tid : tid - 64, nt = last ? 256 : 192;
+      for (int e = t0; e < RW * CB; e += nt) {
         const int row = e / CB, k = c0 + e % CB;
         if (r0 + row < mr && k < nbe) M[(r0 + row) * ld + p + k] = S[row * LDQ + k];
       }
