@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(int m, const double* __restric
 
   // acc_c = sum over later blocks qb of sum_i L[i][c0 + c] y[i]; lane =
   // column c, wavefront w takes rows 16 w .. 16 w + 15 of each block: one
-  // 128-byte line of y, which it polls through a single entry first
+  // 128-byte line of y, which it polls with one coalesced load
   double acc = 0.0;
   bool abort = false;
   for (int qb = nblk - 1; qb > rb && !abort; --qb) {
@@ -221,19 +221,15 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(int m, const double* __restric
     for (int k = 0; k < SB; ++k)
       lv[k] = (lane < cols && k < nr) ? L[(long)(qb * TB + r0 + k) * ld + c0 + lane] : 0.0;
     for (int spins = 0;; ++spins) {
-      bool pend = true;
-      if (!pending(__hip_atomic_load(&yq[nr - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-        pend = false;
+      // lane k loads entry k % 16 of the line: one coalesced access per poll,
+      // and once none is pending the values are already here
+      const int k16 = min(lane & (SB - 1), nr - 1);
+      const double v = __hip_atomic_load(&yq[k16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!__any(pending(v))) {
 #pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          yv[k] = 0.0;
-          if (k < nr) {
-            yv[k] = __hip_atomic_load(&yq[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            pend |= pending(yv[k]);
-          }
-        }
+        for (int k = 0; k < SB; ++k) yv[k] = (k < nr) ? readlane_d(v, k) : 0.0;
+        break;
       }
-      if (!__any(pend)) break;
       if (spins > kSpinLimit ||
           __hip_atomic_load(&info->trsv_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         if (lane == 0) atomicOr(&info->trsv_err, 1);

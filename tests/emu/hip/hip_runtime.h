@@ -133,11 +133,6 @@ inline int __any(int p) {
   g_wave_bar[w].wait();
   return r;
 }
-// the written value is a scalar register on the hardware: the first lane's
-inline int __builtin_amdgcn_writelane(int v, int lane, int old) {
-  const int u = emu_exchange(v, 0);
-  return (threadIdx.x & 63) == (lane & 63) ? u : old;
-}
 
 inline double __builtin_amdgcn_mfma_f64_4x4x4f64(double a, double b, double c, int, int, int) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
