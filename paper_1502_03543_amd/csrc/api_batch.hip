@@ -138,6 +138,7 @@ struct lp_batch {
   BatchAdj adj{};             // reverse-sweep pools (with a tape)
   int max_iters_run = 0;
   int max_m = 0;
+  std::vector<int> order;     // descriptor slot -> caller's LP index
 };
 
 namespace {
@@ -273,6 +274,21 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
   Carver cv(workspace);
   carve_batch(h, m, n, cv);
   for (int i = 0; i < count; ++i) h->lps_h[i].a_off = a_off[i];
+  // Descriptors (and every per-LP device array indexed like them) in
+  // decreasing order of normal-matrix work m^2 n: the per-LP kernels hand
+  // out their workgroups in descriptor order, so the longest start first
+  // instead of forming a tail.  Pool offsets stay in the caller's order;
+  // statuses go back through `order`.
+  h->order.resize(count);
+  for (int i = 0; i < count; ++i) h->order[i] = i;
+  auto work = [&](int i) { return (double)m[i] * (double)m[i] * (double)n[i]; };
+  std::stable_sort(h->order.begin(), h->order.end(),
+                   [&](int x, int y) { return work(x) > work(y); });
+  {
+    std::vector<BatchLP> by_slot(count);
+    for (int k = 0; k < count; ++k) by_slot[k] = h->lps_h[h->order[k]];
+    h->lps_h.swap(by_slot);
+  }
   BatchArgs& a = h->args;
   a.A = A_packed;
   a.lps = h->lps;
@@ -280,7 +296,11 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
   a.alpha = h->opt.alpha;
   for (int i = 0; i < count; ++i) h->max_m = std::max(h->max_m, (int)m[i]);
   hipStream_t s = h->st;
-  std::vector<long long> uvm(v_off_m, v_off_m + count), uvn(v_off_n, v_off_n + count);
+  std::vector<long long> uvm(count), uvn(count);
+  for (int k = 0; k < count; ++k) {
+    uvm[k] = v_off_m[h->order[k]];
+    uvn[k] = v_off_n[h->order[k]];
+  }
   long long* d_uvm = h->uvm;
   long long* d_uvn = h->uvn;
   hipError_t e =
@@ -375,12 +395,13 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
   if (e != hipSuccess) return LP_ERR_DEVICE;
   int conv = 0;
   h->max_iters_run = 0;
-  for (int i = 0; i < h->count; ++i) {
-    h->max_iters_run = std::max(h->max_iters_run, states[i].iters);
-    int stt = states[i].status;
+  for (int k = 0; k < h->count; ++k) {
+    const int i = h->order[k];  // slot k holds the caller's LP i
+    h->max_iters_run = std::max(h->max_iters_run, states[k].iters);
+    int stt = states[k].status;
     if (stt == LP_OK) stt = LP_MAX_ITER;  // never reached with max_launches above
     if (status) status[i] = stt;
-    if (iters) iters[i] = states[i].iters;
+    if (iters) iters[i] = states[k].iters;
     conv += (stt == LP_CONVERGED || stt == LP_OPTIMAL_PSI1);
   }
   if (n_converged) *n_converged = conv;
