@@ -142,6 +142,60 @@ def batch_variant(lpgen, solver, capi, torch, sample: int = 32) -> dict:
     }
 
 
+def adjoint_variant(lpgen, solver, capi, torch, cpu: bool) -> dict:
+    """64 LPs, m = 256, n = 1024 (seeds 0..63), exactly K = 30 steps at alpha
+    0.9 with a tape, then the reverse sweep of w^T x_K: forward plus backward
+    for the whole batch, timed after setup (a first run warms up).  With
+    `cpu`, the oracle's forward K steps and reverse sweep for LP 0 beside it."""
+    import numpy as np
+
+    K, m, n, count = 30, 256, 1024, 64
+    lps = [lpgen.gen_lp(m, n, i) for i in range(count)]
+    wcat = torch.from_numpy(
+        np.concatenate([lpgen.loss_weights(n, i) for i in range(count)])).to("cuda:0")
+
+    def run():
+        bt = solver.Batch(lps, alpha=0.9, tape_capacity=K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = bt.solve(0.0, K)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bt.backward(wcat)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ok = all(capi.status_string(int(v)) == "LP_MAX_ITER" for v in res["status"])
+        bt.close()
+        return t1 - t0, t2 - t1, ok
+
+    run()
+    tf, tb, ok = run()
+    out = {
+        "workload": f"{count} LPs m={m} n={n} (seeds 0..{count - 1}), K={K} steps at alpha 0.9 "
+                    "with a tape, then the reverse sweep of w^T x_K (w from stream 5), FP64",
+        "lps_per_s": count / (tf + tb),
+        "forward_ms": 1e3 * tf,
+        "backward_ms": 1e3 * tb,
+        "all_took_K_steps": ok,
+    }
+    if cpu:
+        import oracle
+
+        ns = 4
+        t0 = time.perf_counter()
+        for i in range(ns):
+            lp = lps[i]
+            r = oracle.solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.9, 0.0, K, tape=True)
+            oracle.backward(lp.A, lp.b, lp.c, 0.9, K, r.tape, lpgen.loss_weights(n, i))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": ns / dt, "unit": "LPs/s (forward K steps + reverse sweep)",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"LPs 0..{ns - 1} of the {count}: oracle forward {K} steps with tape and "
+                      f"reverse sweep, {dt:.2f} s"}
+    return out
+
+
 def mixed_compare():
     """m=8192, n=32768: one mixed-precision solve and one FP64 solve from the
     same start, with the per-iteration precision and refinement counts."""
@@ -319,7 +373,10 @@ def main():
     for h in handles:
         h.close()
     if not args.no_variants:
-        out["variants"] = {"batched": batch_variant(lpgen, solver, capi, torch)}
+        out["variants"] = {
+            "batched": batch_variant(lpgen, solver, capi, torch),
+            "adjoint": adjoint_variant(lpgen, solver, capi, torch, not args.no_cpu_baseline),
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lp, K, args.cpu_sample_iters)
     print(json.dumps(out))
