@@ -12,7 +12,9 @@ Prints one JSON line: LP solves/s, plus the normal-matrix kernel's roofline
 timed on a bounded sample of the same workload.
 
 The same line carries the batched comparison (512 ragged LPs solved together
-against the single-LP FP64 solver applied LP by LP on a sample of them).
+against the single-LP FP64 solver applied LP by LP on a sample of them) and
+the reverse-mode workload (64 LPs, K = 30 steps with a tape plus the reverse
+sweep, with the oracle's forward and reverse sweep on a sample beside it).
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants]
   python bench.py --mixed-compare   # m=8192, n=32768: mixed precision vs FP64, one solve each
