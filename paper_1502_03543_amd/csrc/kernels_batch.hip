@@ -497,9 +497,11 @@ __global__ __launch_bounds__(256) void k_badj(BatchArgs a, BatchAdj g, int k) {
     dsb[j] = dsbj;
   }
   __syncthreads();
-  // dybar = t ybar - A dsbar
+  // dybar = t ybar - A dsbar (the row and column loops of this kernel are
+  // unrolled so their loads run ahead of the in-order sums)
   for (int i = wv; i < m; i += 4) {
     double acc = 0.0;
+#pragma unroll 8
     for (int j = lane; j < n; j += 64) acc += V.A[(long)i * n + j] * dsb[j];
     acc = wsum(acc);
     if (lane == 0) dyb[i] = t * yb[i] - acc;
@@ -511,6 +513,7 @@ __global__ __launch_bounds__(256) void k_badj(BatchArgs a, BatchAdj g, int k) {
   // h = A^T lambda, then d, rhs and r_d in reverse
   for (int j = tid; j < n; j += 256) {
     double h = 0.0;
+#pragma unroll 16
     for (int i = 0; i < m; ++i) h += V.A[(long)i * n + j] * lam[i];
     hv[j] = h;
     double dbj = db[j];
@@ -527,6 +530,7 @@ __global__ __launch_bounds__(256) void k_badj(BatchArgs a, BatchAdj g, int k) {
   // ybar -= A rdbar
   for (int i = wv; i < m; i += 4) {
     double acc = 0.0;
+#pragma unroll 8
     for (int j = lane; j < n; j += 64) acc += V.A[(long)i * n + j] * rdb[j];
     acc = wsum(acc);
     if (lane == 0) yb[i] -= acc;
@@ -536,6 +540,7 @@ __global__ __launch_bounds__(256) void k_badj(BatchArgs a, BatchAdj g, int k) {
     double* Ab = g.Abar + P.a_off;
     for (int i = wv; i < m; i += 4) {
       const double u1 = V.dy[i], u2 = lam[i], u3 = y[i];
+#pragma unroll 4
       for (int j = lane; j < n; j += 64) {
         const double v1 = -dsb[j] - hv[j] * V.d[j];
         const double v2 = V.d[j] * rd[j] - V.g[j] * V.d[j];
