@@ -106,8 +106,10 @@ __device__ void wg_trsv_bwd(int m, const double* L, long ld, const double* z, do
       Ld[ii * (BT + 1) + k] = v;
     }
     double acc = 0.0;
-    if (lane < cols)
+    if (lane < cols) {
+#pragma unroll 8
       for (int i = c0 + BT + wv; i < m; i += 4) acc += L[(long)i * ld + c0 + lane] * out[i];
+    }
     sacc[wv * BT + lane] = acc;
     __syncthreads();
     if (wv == 0) {
