@@ -96,16 +96,6 @@ __global__ void k_batch_copy_cur(int count, const BatchLP* lps, const BatchState
     if (y) y[P.vm + i] = yb[cur][P.vm + i];
 }
 
-// Zero LP i's region of a matrix packed like A (offset a_off).
-__global__ void k_batch_zero_mats(int count, const BatchLP* lps, double* Ab) {
-  const int lp = blockIdx.y;
-  if (lp >= count) return;
-  const BatchLP P = lps[lp];
-  const long mn = (long)P.m * P.n;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn; e += (long)gridDim.x * blockDim.x)
-    Ab[P.a_off + e] = 0.0;
-}
-
 __global__ void k_batch_tape_row(int count, const BatchLP* lps, const BatchState* st,
                                  const double* tape, int k, double* x, double* y, double* s) {
   const int lp = blockIdx.x;
@@ -138,6 +128,7 @@ struct lp_batch {
   BatchAdj adj{};             // reverse-sweep pools (with a tape)
   int max_iters_run = 0;
   int max_m = 0;
+  int max_tiles = 0;          // 64 x 64 tiles of the largest A (for Abar)
   std::vector<int> order;     // descriptor slot -> caller's LP index
 };
 
@@ -225,6 +216,10 @@ void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
     g.cbar = cv.take<double>(vn);
     g.err = cv.take<int>(1);
     g.Abar = nullptr;
+    g.sm = vm;
+    g.sn = vn;
+    g.ufac = cv.take<double>((long)tape_cap * 3 * vm);
+    g.vfac = cv.take<double>((long)tape_cap * 3 * vn);
   }
 }
 
@@ -294,7 +289,10 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
   a.lps = h->lps;
   a.state = h->state;
   a.alpha = h->opt.alpha;
-  for (int i = 0; i < count; ++i) h->max_m = std::max(h->max_m, (int)m[i]);
+  for (int i = 0; i < count; ++i) {
+    h->max_m = std::max(h->max_m, (int)m[i]);
+    h->max_tiles = std::max(h->max_tiles, (int)(((m[i] + 63) / 64) * ((n[i] + 63) / 64)));
+  }
   hipStream_t s = h->st;
   std::vector<long long> uvm(count), uvn(count);
   for (int k = 0; k < count; ++k) {
@@ -433,9 +431,8 @@ lp_status lp_batch_backward(lp_batch* h, const double* xbar_K, const double* yba
   launch_zero(s, g.bbar, h->sum_m);
   launch_zero(s, g.cbar, h->sum_n);
   launch_fill_i32(s, g.err, 0, 1);
-  if (Abar) hipLaunchKernelGGL(k_batch_zero_mats, dim3(64, h->count), dim3(256), 0, s, h->count,
-                               h->lps, Abar);
   for (int k = h->max_iters_run - 1; k >= 0; --k) launch_batch_step(s, a, h->max_m, k, &g);
+  if (Abar) launch_babar(s, h->count, h->max_tiles, h->lps, h->state, g, a.tape_cap, Abar);
   if (x0bar) launch_copy(s, x0bar, g.xb, h->sum_n);
   if (y0bar) launch_copy(s, y0bar, g.yb, h->sum_m);
   if (s0bar) launch_copy(s, s0bar, g.sb, h->sum_n);

@@ -537,19 +537,58 @@ __global__ __launch_bounds__(256) void k_badj(BatchArgs a, BatchAdj g, int k) {
     acc = wsum(acc);
     if (lane == 0) yb[i] -= acc;
   }
-  // Abar += dy v1^T + lambda v2^T + y v3^T
+  // this step's share of Abar, dy v1^T + lambda v2^T + y v3^T: the six
+  // vectors are kept (slot k) and the products formed once after the sweep
+  // (k_babar), instead of reading and writing all of Abar every step
   if (g.Abar) {
-    double* Ab = g.Abar + P.a_off;
-    for (int i = wv; i < m; i += 4) {
-      const double u1 = V.dy[i], u2 = lam[i], u3 = y[i];
-#pragma unroll 4
-      for (int j = lane; j < n; j += 64) {
-        const double v1 = -dsb[j] - hv[j] * V.d[j];
-        const double v2 = V.d[j] * rd[j] - V.g[j] * V.d[j];
-        const double v3 = -rdb[j];
-        Ab[(long)i * n + j] += u1 * v1 + u2 * v2 + u3 * v3;
-      }
+    double* U = g.ufac + (long)k * 3 * g.sm + P.vm;
+    double* W = g.vfac + (long)k * 3 * g.sn + P.vn;
+    for (int i = tid; i < m; i += 256) {
+      U[i] = V.dy[i];
+      U[g.sm + i] = lam[i];
+      U[2 * g.sm + i] = y[i];
     }
+    for (int j = tid; j < n; j += 256) {
+      W[j] = -dsb[j] - hv[j] * V.d[j];
+      W[g.sn + j] = V.d[j] * rd[j] - V.g[j] * V.d[j];
+      W[2 * g.sn + j] = -rdb[j];
+    }
+  }
+}
+
+// Abar of LP blockIdx.y, 64 x 64 tile blockIdx.x: the sum over the steps the
+// sweep reversed (last first, as it ran) of dy v1^T + lambda v2^T + y v3^T,
+// each step's three products added as one term.  Thread t: column t % 64,
+// rows t / 64 + 4 e.
+__global__ __launch_bounds__(256) void k_babar(const BatchLP* __restrict__ lps,
+                                               const BatchState* __restrict__ st, BatchAdj g,
+                                               int tape_cap, double* __restrict__ Abar) {
+  const int lp = blockIdx.y;
+  const BatchLP P = lps[lp];
+  const int tn = (P.n + 63) / 64, tm = (P.m + 63) / 64;
+  const int t = blockIdx.x;
+  if (t >= tm * tn) return;
+  const int r0 = (t / tn) * 64, j = (t % tn) * 64 + (threadIdx.x & 63), rw = threadIdx.x >> 6;
+  if (j >= P.n) return;
+  const int nk = min(st[lp].iters, tape_cap);
+  double acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+  for (int k = nk - 1; k >= 0; --k) {
+    const double* U = g.ufac + (long)k * 3 * g.sm + P.vm;
+    const double* W = g.vfac + (long)k * 3 * g.sn + P.vn;
+    const double v1 = W[j], v2 = W[g.sn + j], v3 = W[2 * g.sn + j];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = min(r0 + rw + 4 * e, P.m - 1);
+      acc[e] += U[i] * v1 + U[g.sm + i] * v2 + U[2 * g.sm + i] * v3;
+    }
+  }
+  double* Ab = Abar + P.a_off;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int i = r0 + rw + 4 * e;
+    if (i < P.m) Ab[(long)i * P.n + j] = acc[e];
   }
 }
 
@@ -607,6 +646,12 @@ void launch_batch_step(hipStream_t st, const BatchArgs& a, int max_m, int k,
   hipLaunchKernelGGL(k_bdir, dim3(count), dim3(256), 0, st, a, k, err);
   if (k < 0) hipLaunchKernelGGL(k_bstep, dim3(count), dim3(256), 0, st, a);
   else hipLaunchKernelGGL(k_badj, dim3(count), dim3(256), 0, st, a, *adj, k);
+}
+
+void launch_babar(hipStream_t st, int count, int max_tiles, const BatchLP* lps,
+                  const BatchState* state, const BatchAdj& adj, int tape_cap, double* Abar) {
+  hipLaunchKernelGGL(k_babar, dim3(max_tiles, count), dim3(256), 0, st, lps, state, adj,
+                     tape_cap, Abar);
 }
 
 void launch_batch_setup(hipStream_t st, int count, const BatchLP* lps, BatchState* state,

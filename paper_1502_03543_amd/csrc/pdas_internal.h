@@ -191,6 +191,10 @@ struct BatchAdj {
   double *xb, *yb, *sb, *dsb, *db, *dyb, *lam, *h, *rdb, *bbar, *cbar;
   double* Abar;  // caller's output, may be null
   int* err;
+  // Abar's rank-3 terms of every reverse step k, formed once after the sweep:
+  // ufac[(3 k + r) sm + vm + i] and vfac[(3 k + r) sn + vn + j], r = 0..2
+  double *ufac, *vfac;
+  long sm, sn;
 };
 
 // One forward iteration of every active LP (k < 0), or the recomputation
@@ -198,6 +202,10 @@ struct BatchAdj {
 // whose shapes depend only on count and max_m (so it can be captured once).
 void launch_batch_step(hipStream_t st, const BatchArgs& args, int max_m, int k,
                        const BatchAdj* adj);
+// Abar of every LP from the factors the reverse sweep stored (steps taken
+// by that LP, capped at tape_cap), in 64 x 64 tiles (max_tiles per LP).
+void launch_babar(hipStream_t st, int count, int max_tiles, const BatchLP* lps,
+                  const BatchState* state, const BatchAdj& adj, int tape_cap, double* Abar);
 void launch_batch_setup(hipStream_t st, int count, const BatchLP* lps, BatchState* state,
                         const double* Ap, const double* c, const double* x, const double* y,
                         const double* s, double* rd);
