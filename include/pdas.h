@@ -257,8 +257,9 @@ lp_status lp_batch_get_iterate(const lp_batch* h, double* x, double* y, double* 
  * lp_batch_get_iterate's outputs; Abar (nullable) is packed like A_packed
  * (offsets a_off); bbar, cbar, x0bar, y0bar, s0bar (nullable) are packed like
  * the iterates.  Every recorded step is recomputed from its start iterate and
- * dual residual in FP64 and its Cholesky factor serves the solve with M.
- * Synchronises. */
+ * dual residual in FP64 and its Cholesky factor serves the solve with M; the
+ * steps' rank-3 terms of Abar are kept in the workspace and summed once after
+ * the sweep.  Synchronises. */
 lp_status lp_batch_backward(lp_batch* h, const double* xbar_K, const double* ybar_K,
                             const double* sbar_K, double* Abar, double* bbar, double* cbar,
                             double* x0bar, double* y0bar, double* s0bar);
