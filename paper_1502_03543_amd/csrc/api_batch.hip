@@ -218,6 +218,8 @@ void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
     g.Abar = nullptr;
     g.sm = vm;
     g.sn = vn;
+    g.max_n = 0;
+    for (int i = 0; i < count; ++i) g.max_n = std::max(g.max_n, (int)n[i]);
     g.ufac = cv.take<double>((long)tape_cap * 3 * vm);
     g.vfac = cv.take<double>((long)tape_cap * 3 * vn);
   }

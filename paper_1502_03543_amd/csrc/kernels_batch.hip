@@ -16,9 +16,11 @@
 //   k_bdir          per LP: g = A^T dy, g_y = A^T y, ds, dx, ratio test
 //   k_bstep         per LP: step, next r_d, gap, statuses
 // The reverse sweep recomputes step k from its tape row with the same
-// launches (k_bbegin reads the tape instead of the iterate) and ends with
-// k_badj in place of k_bstep.  LPs that stopped skip every launch (a flag
-// per LP), so a replay costs nothing for them.
+// launches (k_bbegin reads the tape instead of the iterate) and ends with the
+// five reverse launches k_badj_t, k_badj_dyb, k_badj_solve, k_badj_h and
+// k_badj_yb in place of k_bstep; k_babar forms Abar once after the sweep.
+// LPs that stopped skip every launch (a flag per LP), so a replay costs
+// nothing for them.
 #include <climits>
 #include <cmath>
 
@@ -448,12 +450,32 @@ __global__ __launch_bounds__(256) void k_bstep(BatchArgs a) {
 // Reverse of the recomputed step k of LP blockIdx.x (same order as the
 // single-LP reverse sweep).  Abar (packed like A) accumulates three outer
 // products per step.
-__global__ __launch_bounds__(256) void k_badj(BatchArgs a, BatchAdj g, int k) {
-  __shared__ double lds[4 * BT + BT * (BT + 1)];
+// The reverse step runs as five launches: the per-LP scalar part and the
+// triangular solves take one workgroup per LP, the three products with A
+// (A dsbar, A^T lambda, A rdbar) one wavefront per row or one thread per
+// column across all LPs, each sum in the same order as a single workgroup
+// would take it.
+struct AdjPtrs {
+  double *xb, *yb, *sb, *dsb, *db, *dyb, *lam, *hv, *rdb, *bb, *cb;
+};
+__device__ inline AdjPtrs adj_ptrs(const BatchAdj& g, const BatchLP& P) {
+  return AdjPtrs{g.xb + P.vn,   g.yb + P.vm, g.sb + P.vn,  g.dsb + P.vn,
+                 g.db + P.vn,   g.dyb + P.vm, g.lam + P.vm, g.h + P.vn,
+                 g.rdb + P.vn,  g.bbar + P.vm, g.cbar + P.vn};
+}
+__device__ inline double adj_t(const BatchArgs& a, int lp) {
+  const double psi = a.psi[lp];
+  const double aeff = (psi == 1.0) ? 1.0 : a.alpha;
+  return aeff / psi;
+}
+
+// 1. tbar = xbar.dx + ybar.dy + sbar.ds, the ratio test and the step in
+//    reverse (one workgroup per LP)
+__global__ __launch_bounds__(256) void k_badj_t(BatchArgs a, BatchAdj g, int k) {
   __shared__ double sh[4];
   const int lp = blockIdx.x;
   if (!a.go[lp]) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   const BatchLP P = a.lps[lp];
   const int m = P.m, n = P.n;
   const LPView V = lp_view(a, P);
@@ -461,29 +483,18 @@ __global__ __launch_bounds__(256) void k_badj(BatchArgs a, BatchAdj g, int k) {
   lp_source(a, P, 0, k, x, y, s, rd);
   const double psi = a.psi[lp];
   const long long J = a.arg[lp];
-  double* xb = g.xb + P.vn;
-  double* yb = g.yb + P.vm;
-  double* sb = g.sb + P.vn;
-  double* dsb = g.dsb + P.vn;
-  double* db = g.db + P.vn;
-  double* dyb = g.dyb + P.vm;
-  double* lam = g.lam + P.vm;
-  double* hv = g.h + P.vn;
-  double* rdb = g.rdb + P.vn;
-  double* bb = g.bbar + P.vm;
-  double* cb = g.cbar + P.vn;
-  // tbar = xbar.dx + ybar.dy + sbar.ds
+  const AdjPtrs q = adj_ptrs(g, P);
   double tp = 0.0;
-  for (int j = tid; j < n; j += 256) tp += xb[j] * V.dx[j] + sb[j] * V.ds[j];
-  for (int i = tid; i < m; i += 256) tp += yb[i] * V.dy[i];
+  for (int j = tid; j < n; j += 256) tp += q.xb[j] * V.dx[j] + q.sb[j] * V.ds[j];
+  for (int i = tid; i < m; i += 256) tp += q.yb[i] * V.dy[i];
   const double tbar = bsum(tp, sh);
   const double aeff = (psi == 1.0) ? 1.0 : a.alpha;
   const double t = aeff / psi;
   const double psib = -aeff * tbar / (psi * psi);
   for (int j = tid; j < n; j += 256) {
-    double dxb = t * xb[j];
-    double dsbj = t * sb[j];
-    double xbj = xb[j], sbj = sb[j];
+    double dxb = t * q.xb[j];
+    double dsbj = t * q.sb[j];
+    double xbj = q.xb[j], sbj = q.sb[j];
     if (J == j) {
       dxb += -psib / x[j];
       xbj += psib * V.dx[j] / (x[j] * x[j]);
@@ -492,66 +503,105 @@ __global__ __launch_bounds__(256) void k_badj(BatchArgs a, BatchAdj g, int k) {
       sbj += psib * V.ds[j] / (s[j] * s[j]);
     }
     xbj -= dxb;
-    db[j] = -dxb * V.ds[j];
+    q.db[j] = -dxb * V.ds[j];
     dsbj -= V.d[j] * dxb;
-    xb[j] = xbj;
-    sb[j] = sbj;
-    dsb[j] = dsbj;
+    q.xb[j] = xbj;
+    q.sb[j] = sbj;
+    q.dsb[j] = dsbj;
   }
-  __syncthreads();
-  // dybar = t ybar - A dsbar (the row and column loops of this kernel are
-  // unrolled so their loads run ahead of the in-order sums)
-  for (int i = wv; i < m; i += 4) {
-    double acc = 0.0;
+}
+
+// 2. dybar = t ybar - A dsbar: one wavefront per row (blockIdx.x * 4 + wave)
+__global__ __launch_bounds__(256) void k_badj_dyb(BatchArgs a, BatchAdj g) {
+  const int lp = blockIdx.y;
+  if (!a.go[lp]) return;
+  const BatchLP P = a.lps[lp];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= P.m) return;
+  const int n = P.n;
+  const double* Ai = a.A + P.a_off + (long)i * n;
+  const double* dsb = g.dsb + P.vn;
+  double acc = 0.0;
 #pragma unroll 8
-    for (int j = lane; j < n; j += 64) acc += V.A[(long)i * n + j] * dsb[j];
-    acc = wsum(acc);
-    if (lane == 0) dyb[i] = t * yb[i] - acc;
-  }
-  __syncthreads();
-  // lambda = M^-1 dybar with the recomputed factor
-  wg_trsv_fwd(m, V.M, V.ldm, dyb, V.z, lds);
-  wg_trsv_bwd(m, V.M, V.ldm, V.z, lam, lds);
-  // h = A^T lambda, then d, rhs and r_d in reverse
-  for (int j = tid; j < n; j += 256) {
-    double h = 0.0;
+  for (int j = lane; j < n; j += 64) acc += Ai[j] * dsb[j];
+  acc = wsum(acc);
+  if (lane == 0) g.dyb[P.vm + i] = adj_t(a, lp) * g.yb[P.vm + i] - acc;
+}
+
+// 3. lambda = M^-1 dybar with the recomputed factor (one workgroup per LP)
+__global__ __launch_bounds__(256) void k_badj_solve(BatchArgs a, BatchAdj g) {
+  __shared__ double lds[4 * BT + BT * (BT + 1)];
+  const int lp = blockIdx.x;
+  if (!a.go[lp]) return;
+  const BatchLP P = a.lps[lp];
+  const LPView V = lp_view(a, P);
+  wg_trsv_fwd(P.m, V.M, V.ldm, g.dyb + P.vm, V.z, lds);
+  wg_trsv_bwd(P.m, V.M, V.ldm, V.z, g.lam + P.vm, lds);
+}
+
+// 4. h = A^T lambda (one thread per column, rows in order), then d, rhs and
+//    r_d in reverse; bbar += lambda; the column vectors of this step's share
+//    of Abar (slot k)
+__global__ __launch_bounds__(256) void k_badj_h(BatchArgs a, BatchAdj g, int k) {
+  const int lp = blockIdx.y;
+  if (!a.go[lp]) return;
+  const BatchLP P = a.lps[lp];
+  const int m = P.m, n = P.n;
+  const LPView V = lp_view(a, P);
+  const double *x, *y, *s, *rd;
+  lp_source(a, P, 0, k, x, y, s, rd);
+  const AdjPtrs q = adj_ptrs(g, P);
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < m; i += 256) q.bb[i] += q.lam[i];
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double h = 0.0;
 #pragma unroll 16
-    for (int i = 0; i < m; ++i) h += V.A[(long)i * n + j] * lam[i];
-    hv[j] = h;
-    double dbj = db[j];
-    dbj -= h * V.g[j];
-    dbj += rd[j] * h;
-    const double rdbj = dsb[j] + V.d[j] * h;
-    xb[j] += dbj / s[j];
-    sb[j] = sb[j] - dbj * x[j] / (s[j] * s[j]) - rdbj;
-    cb[j] += rdbj;
-    rdb[j] = rdbj;
-  }
-  for (int i = tid; i < m; i += 256) bb[i] += lam[i];
-  __syncthreads();
-  // ybar -= A rdbar
-  for (int i = wv; i < m; i += 4) {
-    double acc = 0.0;
-#pragma unroll 8
-    for (int j = lane; j < n; j += 64) acc += V.A[(long)i * n + j] * rdb[j];
-    acc = wsum(acc);
-    if (lane == 0) yb[i] -= acc;
-  }
+  for (int i = 0; i < m; ++i) h += V.A[(long)i * n + j] * q.lam[i];
+  q.hv[j] = h;
+  double dbj = q.db[j];
+  dbj -= h * V.g[j];
+  dbj += rd[j] * h;
+  const double rdbj = q.dsb[j] + V.d[j] * h;
+  q.xb[j] += dbj / s[j];
+  q.sb[j] = q.sb[j] - dbj * x[j] / (s[j] * s[j]) - rdbj;
+  q.cb[j] += rdbj;
+  q.rdb[j] = rdbj;
   // this step's share of Abar, dy v1^T + lambda v2^T + y v3^T: the six
   // vectors are kept (slot k) and the products formed once after the sweep
   // (k_babar), instead of reading and writing all of Abar every step
   if (g.Abar) {
-    double* U = g.ufac + (long)k * 3 * g.sm + P.vm;
     double* W = g.vfac + (long)k * 3 * g.sn + P.vn;
-    for (int i = tid; i < m; i += 256) {
-      U[i] = V.dy[i];
-      U[g.sm + i] = lam[i];
+    W[j] = -q.dsb[j] - h * V.d[j];
+    W[g.sn + j] = V.d[j] * rd[j] - V.g[j] * V.d[j];
+    W[2 * g.sn + j] = -rdbj;
+  }
+}
+
+// 5. ybar -= A rdbar (one wavefront per row); the row vectors of the step's
+//    share of Abar
+__global__ __launch_bounds__(256) void k_badj_yb(BatchArgs a, BatchAdj g, int k) {
+  const int lp = blockIdx.y;
+  if (!a.go[lp]) return;
+  const BatchLP P = a.lps[lp];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= P.m) return;
+  const int n = P.n;
+  const double* Ai = a.A + P.a_off + (long)i * n;
+  const double* rdb = g.rdb + P.vn;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int j = lane; j < n; j += 64) acc += Ai[j] * rdb[j];
+  acc = wsum(acc);
+  if (lane == 0) {
+    g.yb[P.vm + i] -= acc;
+    if (g.Abar) {
+      const double *x, *y, *s, *rd;
+      lp_source(a, P, 0, k, x, y, s, rd);
+      double* U = g.ufac + (long)k * 3 * g.sm + P.vm;
+      U[i] = a.dy[P.vm + i];
+      U[g.sm + i] = g.lam[P.vm + i];
       U[2 * g.sm + i] = y[i];
-    }
-    for (int j = tid; j < n; j += 256) {
-      W[j] = -dsb[j] - hv[j] * V.d[j];
-      W[g.sn + j] = V.d[j] * rd[j] - V.g[j] * V.d[j];
-      W[2 * g.sn + j] = -rdb[j];
     }
   }
 }
@@ -645,7 +695,14 @@ void launch_batch_step(hipStream_t st, const BatchArgs& a, int max_m, int k,
   hipLaunchKernelGGL(k_btrsv, dim3(count), dim3(256), 0, st, a, k, err);
   hipLaunchKernelGGL(k_bdir, dim3(count), dim3(256), 0, st, a, k, err);
   if (k < 0) hipLaunchKernelGGL(k_bstep, dim3(count), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(k_badj, dim3(count), dim3(256), 0, st, a, *adj, k);
+  else {
+    hipLaunchKernelGGL(k_badj_t, dim3(count), dim3(256), 0, st, a, *adj, k);
+    hipLaunchKernelGGL(k_badj_dyb, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a, *adj);
+    hipLaunchKernelGGL(k_badj_solve, dim3(count), dim3(256), 0, st, a, *adj);
+    hipLaunchKernelGGL(k_badj_h, dim3(cdiv(adj->max_n, 256), count), dim3(256), 0, st, a, *adj,
+                       k);
+    hipLaunchKernelGGL(k_badj_yb, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a, *adj, k);
+  }
 }
 
 void launch_babar(hipStream_t st, int count, int max_tiles, const BatchLP* lps,

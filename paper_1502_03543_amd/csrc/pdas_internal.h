@@ -195,6 +195,7 @@ struct BatchAdj {
   // ufac[(3 k + r) sm + vm + i] and vfac[(3 k + r) sn + vn + j], r = 0..2
   double *ufac, *vfac;
   long sm, sn;
+  int max_n;  // largest n of the batch (grid of the column-wise launch)
 };
 
 // One forward iteration of every active LP (k < 0), or the recomputation
