@@ -50,6 +50,29 @@ __device__ inline void amerge(double& v, long long& i, double v2, long long i2) 
   }
 }
 
+// The 64 x 64 diagonal block at (i0, i0) (rows < nr kept, identity beyond,
+// upper part zero) as staged in LDS, held by wavefronts 1..3 in registers:
+// element e = (tid - 64) + 192 q of the block, q < kPre.
+constexpr int kPre = (BT * BT + 191) / 192;
+__device__ inline void diag_load(const double* L, long ld, int i0, int nr, int tid,
+                                 double (&pre)[kPre]) {
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    const int e = (tid - 64) + 192 * q;
+    const int ii = e / BT, k = e % BT;
+    double v = (ii == k) ? 1.0 : 0.0;
+    if (e < BT * BT && ii < nr && k <= ii) v = L[(long)(i0 + ii) * ld + i0 + k];
+    pre[q] = v;
+  }
+}
+__device__ inline void diag_store(double* Ld, int tid, const double (&pre)[kPre]) {
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    const int e = (tid - 64) + 192 * q;
+    if (e < BT * BT) Ld[(e / BT) * (BT + 1) + e % BT] = pre[q];
+  }
+}
+
 // z = L^-1 r (forward) into out; L row-major lower with ld.  One workgroup:
 // per 64-row block, all threads form the off-diagonal product and stage the
 // diagonal block in LDS, then wave 0 solves it with readlane broadcasts.
@@ -58,13 +81,18 @@ __device__ void wg_trsv_fwd(int m, const double* L, long ld, const double* r, do
   double* sacc = lds;           // [64]
   double* Ld = lds + BT;        // [64][65]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double pre[kPre];
   for (int i0 = 0; i0 < m; i0 += BT) {
     const int rows = min(BT, m - i0);
-    for (int e = tid; e < BT * BT; e += 256) {
-      const int ii = e / BT, k = e % BT;
-      double v = (ii == k) ? 1.0 : 0.0;
-      if (ii < rows && k <= ii) v = L[(long)(i0 + ii) * ld + i0 + k];
-      Ld[ii * (BT + 1) + k] = v;
+    if (i0 == 0) {
+      for (int e = tid; e < BT * BT; e += 256) {
+        const int ii = e / BT, k = e % BT;
+        double v = (ii == k) ? 1.0 : 0.0;
+        if (ii < rows && k <= ii) v = L[(long)(i0 + ii) * ld + i0 + k];
+        Ld[ii * (BT + 1) + k] = v;
+      }
+    } else if (wv > 0) {
+      diag_store(Ld, tid, pre);
     }
     // wave wv: rows wv, wv+4, ...; lanes over columns 0..i0-1
     for (int ii = wv; ii < BT; ii += 4) {
@@ -75,6 +103,8 @@ __device__ void wg_trsv_fwd(int m, const double* L, long ld, const double* r, do
       if (lane == 0) sacc[ii] = acc;
     }
     __syncthreads();
+    // wavefronts 1..3 load the next diagonal block while wavefront 0 solves
+    if (wv > 0 && i0 + BT < m) diag_load(L, ld, i0 + BT, min(BT, m - i0 - BT), tid, pre);
     if (wv == 0) {
       const double dl = 1.0 / Ld[lane * (BT + 1) + lane];
       double val = (lane < rows) ? (r[i0 + lane] - sacc[lane]) : 0.0;
@@ -99,13 +129,18 @@ __device__ void wg_trsv_bwd(int m, const double* L, long ld, const double* z, do
   double* Ld = lds + 4 * BT;    // [64][65]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nblk = (m + BT - 1) / BT;
+  double pre[kPre];
   for (int rb = nblk - 1; rb >= 0; --rb) {
     const int c0 = rb * BT, cols = min(BT, m - c0);
-    for (int e = tid; e < BT * BT; e += 256) {
-      const int ii = e / BT, k = e % BT;
-      double v = (ii == k) ? 1.0 : 0.0;
-      if (ii < cols && k <= ii) v = L[(long)(c0 + ii) * ld + c0 + k];
-      Ld[ii * (BT + 1) + k] = v;
+    if (rb == nblk - 1) {
+      for (int e = tid; e < BT * BT; e += 256) {
+        const int ii = e / BT, k = e % BT;
+        double v = (ii == k) ? 1.0 : 0.0;
+        if (ii < cols && k <= ii) v = L[(long)(c0 + ii) * ld + c0 + k];
+        Ld[ii * (BT + 1) + k] = v;
+      }
+    } else if (wv > 0) {
+      diag_store(Ld, tid, pre);
     }
     double acc = 0.0;
     if (lane < cols) {
@@ -114,6 +149,8 @@ __device__ void wg_trsv_bwd(int m, const double* L, long ld, const double* z, do
     }
     sacc[wv * BT + lane] = acc;
     __syncthreads();
+    // wavefronts 1..3 load the next diagonal block while wavefront 0 solves
+    if (wv > 0 && rb > 0) diag_load(L, ld, c0 - BT, BT, tid, pre);
     if (wv == 0) {
       const double dl = 1.0 / Ld[lane * (BT + 1) + lane];
       const double tot = ((sacc[lane] + sacc[BT + lane]) + sacc[2 * BT + lane]) + sacc[3 * BT + lane];
