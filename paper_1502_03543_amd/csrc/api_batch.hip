@@ -200,6 +200,14 @@ void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
   a.minp = cv.take<unsigned long long>(count);
   a.psi = cv.take<double>(count);
   a.arg = cv.take<long long>(count);
+  {
+    int max_n = 0;
+    for (int i = 0; i < count; ++i) max_n = std::max(max_n, (int)n[i]);
+    a.nslice = (max_n + 255) / 256;
+  }
+  a.dpv = cv.take<double>((long)count * a.nslice);
+  a.dpi = cv.take<long long>((long)count * a.nslice);
+  a.dpf = cv.take<int>((long)count * a.nslice);
   h->bufptrs = cv.take<double>(6);  // x[2], y[2], s[2] pointers for get_iterate
   if (tape_cap) {
     BatchAdj& g = h->adj;

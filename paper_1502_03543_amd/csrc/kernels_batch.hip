@@ -13,7 +13,9 @@
 //                   k_bsyrk_trailing (the tile routine in subtract mode);
 //                   k_bdiag_to_m puts the diagonal blocks into M at the end
 //   k_btrsv         per LP: L z = rhs, L^T dy = z (64-row blocks, readlane)
-//   k_bdir          per LP: g = A^T dy, g_y = A^T y, ds, dx, ratio test
+//   k_bdir          per LP and 256-column slice: g = A^T dy, g_y = A^T y,
+//                   ds, dx, the slice's ratio-test maximiser
+//   k_bdir_fin      per LP: merged maximiser psi, statuses
 //   k_bstep         per LP: step, next r_d, gap, statuses
 // The reverse sweep recomputes step k from its tape row with the same
 // launches (k_bbegin reads the tape instead of the iterate) and ends with the
@@ -332,18 +334,23 @@ __global__ __launch_bounds__(256) void k_btrsv(BatchArgs a, int k, int* err) {
 }
 
 // g = A^T dy, g_y = A^T y, ds = r_d - g, dx = -x - d o ds, psi and its first
-// maximiser (x block before s block); zero and non-finite directions.
+// maximiser (x block before s block); zero and non-finite directions.  One
+// workgroup per LP and slice of 256 columns (a thread per column), so a large
+// LP's pass over A is spread over several compute units; each slice leaves
+// its maximiser and flags, k_bdir_fin merges them per LP.
 constexpr int kDirStage = 1024;  // dy and y entries staged in LDS per LP
 
-__global__ __launch_bounds__(256) void k_bdir(BatchArgs a, int k, int* err) {
+__global__ __launch_bounds__(256) void k_bdir(BatchArgs a, int k) {
   __shared__ double shv[4];
   __shared__ long long shi[4];
   __shared__ int s_flag, s_cur;
   __shared__ double sdy[kDirStage], sy[kDirStage];
-  const int lp = blockIdx.x;
+  const int lp = blockIdx.y, sl = blockIdx.x;
   if (!a.go[lp]) return;
-  const int tid = threadIdx.x;
   const BatchLP P = a.lps[lp];
+  const int m = P.m, n = P.n;
+  if (sl * 256 >= n) return;
+  const int tid = threadIdx.x;
   if (tid == 0) {
     s_flag = 0;
     s_cur = a.state[lp].cur;
@@ -352,7 +359,6 @@ __global__ __launch_bounds__(256) void k_bdir(BatchArgs a, int k, int* err) {
   const LPView V = lp_view(a, P);
   const double *x, *y, *s, *rd;
   lp_source(a, P, s_cur, k, x, y, s, rd);
-  const int m = P.m, n = P.n;
   double best = -INFINITY;
   long long bi = LLONG_MAX;
   int nz = 0, nf = 0;
@@ -362,9 +368,10 @@ __global__ __launch_bounds__(256) void k_bdir(BatchArgs a, int k, int* err) {
     sy[i] = y[i];
   }
   __syncthreads();
-  for (int j = tid; j < n; j += 256) {
-    // sums in row order as before; the column's A entries are loaded eight
-    // rows ahead so the loads overlap instead of following one another
+  const int j = sl * 256 + tid;
+  if (j < n) {
+    // sums in row order; the column's A entries are loaded eight rows ahead
+    // so the loads overlap instead of following one another
     double g1 = 0.0, g2 = 0.0;
     const double* acol = V.A + j;
     int i = 0;
@@ -400,12 +407,33 @@ __global__ __launch_bounds__(256) void k_bdir(BatchArgs a, int k, int* err) {
     amerge(best, bi, u, j);
     amerge(best, bi, v, n + j);
   }
-  for (int i = tid; i < m; i += 256) nz |= (V.dy[i] != 0.0);
+  if (sl == 0)
+    for (int i = tid; i < m; i += 256) nz |= (V.dy[i] != 0.0);
   if (nz) atomicOr(&s_flag, 1);
   if (nf) atomicOr(&s_flag, 2);
   bargmax(best, bi, shv, shi);
-  const int flags = s_flag;
   if (tid != 0) return;
+  const long o = (long)lp * a.nslice + sl;
+  a.dpv[o] = best;
+  a.dpi[o] = bi;
+  a.dpf[o] = s_flag;
+}
+
+// Per LP (a thread each): merge the slices' maximisers (largest value, then
+// smallest index, so the order of the merge does not matter) and flags into
+// psi, its argmax and the LP's status.
+__global__ __launch_bounds__(256) void k_bdir_fin(BatchArgs a, int k, int* err) {
+  const int lp = blockIdx.x * 256 + threadIdx.x;
+  if (lp >= a.count || !a.go[lp]) return;
+  const int ns = (a.lps[lp].n + 255) / 256;
+  const long o = (long)lp * a.nslice;
+  double best = -INFINITY;
+  long long bi = LLONG_MAX;
+  int flags = 0;
+  for (int q = 0; q < ns; ++q) {
+    amerge(best, bi, a.dpv[o + q], a.dpi[o + q]);
+    flags |= a.dpf[o + q];
+  }
   a.psi[lp] = best;
   a.arg[lp] = bi;
   int st = LP_OK;
@@ -730,7 +758,8 @@ void launch_batch_step(hipStream_t st, const BatchArgs& a, int max_m, int k,
   }
   launch_bdiag_to_m(st, count, max_m, a.lps, a.go, a.M, a.diag);
   hipLaunchKernelGGL(k_btrsv, dim3(count), dim3(256), 0, st, a, k, err);
-  hipLaunchKernelGGL(k_bdir, dim3(count), dim3(256), 0, st, a, k, err);
+  hipLaunchKernelGGL(k_bdir, dim3(a.nslice, count), dim3(256), 0, st, a, k);
+  hipLaunchKernelGGL(k_bdir_fin, dim3(cdiv(count, 256)), dim3(256), 0, st, a, k, err);
   if (k < 0) hipLaunchKernelGGL(k_bstep, dim3(count), dim3(256), 0, st, a);
   else {
     hipLaunchKernelGGL(k_badj_t, dim3(count), dim3(256), 0, st, a, *adj, k);

@@ -184,6 +184,10 @@ struct BatchArgs {
   unsigned long long* minp;  // per LP: smallest pivot (bit pattern of a positive double)
   double* psi;          // per LP: psi of the current direction
   long long* arg;       // per LP: its first maximiser (x block j, s block n + j)
+  int nslice;           // 256-column slices of the widest LP
+  double* dpv;          // per LP and slice: the slice's ratio-test maximum,
+  long long* dpi;       //   its first maximiser
+  int* dpf;             //   and flags (1 nonzero direction, 2 non-finite ratio)
 };
 
 // Adjoint pools of a batch (packed like the forward vectors; Abar like A).

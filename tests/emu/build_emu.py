@@ -9,6 +9,7 @@ AddressSanitizer reports any kernel access that leaves its own pool.
 """
 from __future__ import annotations
 
+import fcntl
 import os
 import shutil
 import subprocess
@@ -37,10 +38,18 @@ def compiler() -> str | None:
 
 
 def build() -> str:
+    """Build under an exclusive lock, so parallel test workers that share the
+    build folder do not rewrite each other's sources mid-compile."""
+    os.makedirs(BUILD, exist_ok=True)
+    with open(os.path.join(BUILD, ".lock"), "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        return _build()
+
+
+def _build() -> str:
     cxx = compiler()
     if cxx is None:
         raise RuntimeError("no clang++ for the kernel emulation")
-    os.makedirs(BUILD, exist_ok=True)
     objs = []
     flags = ["-O1", "-g", "-std=c++20", "-fsanitize=address", "-fno-omit-frame-pointer",
              "-I" + HERE, "-I" + CSRC, "-I" + os.path.join(ROOT, "include"),
