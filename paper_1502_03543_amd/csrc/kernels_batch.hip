@@ -3,8 +3,8 @@
 // normal equations, Cholesky of Section 5.1).
 //
 // One iteration of the whole batch is a fixed sequence of launches whose
-// grids depend only on the batch (count, largest m), so the host captures it
-// once into a hipGraph and replays it:
+// grids depend only on the batch (count, largest m and n), so the host
+// captures it once into a hipGraph and replays it:
 //   k_bbegin        per LP: stop tests, tape row, d = x/s, w = d o r_d
 //   k_brhs          per LP and row group: rhs = b + A w (wavefront per row)
 //   k_bsyrk_normal  per LP and lower 64-tile: M = A D A^T on the FP64 matrix
