@@ -695,7 +695,11 @@ __global__ __launch_bounds__(256) void k_diag_to_m(int m, T* __restrict__ M, lon
 }
 
 // Batched panel step at column p: LP = blockIdx.y (skipped unless it takes a
-// step this iteration and has a panel at p).
+// step this iteration and has a panel at p).  One tile of 16 rows per
+// wavefront: the smaller LDS footprint lets two workgroups share a compute
+// unit, which suits the many short panels of a batch.
+constexpr int kBPanelTPW = 1;
+constexpr int kBPanelRows = PanelShape<kBPanelTPW>::rows;
 __global__ __launch_bounds__(256) void k_bpotrf_panel(const BatchLP* __restrict__ lps,
                                                        const int* __restrict__ go, double* Mpool,
                                                        double* diagpool, int p, int* fail,
@@ -704,9 +708,9 @@ __global__ __launch_bounds__(256) void k_bpotrf_panel(const BatchLP* __restrict_
   const BatchLP P = lps[lp];
   if (!go[lp] || p >= P.m) return;
   const int below = P.m - p - min(NB, P.m - p);
-  if ((int)blockIdx.x > (below + kPanelRows - 1) / kPanelRows) return;
-  __shared__ __attribute__((aligned(16))) double lds[panel_lds_doubles<kPanelTPW>()];
-  potrf_panel_mfma<kPanelTPW>(P.m, P.m, Mpool + P.M_off, P.ldm, p, blockIdx.x,
+  if ((int)blockIdx.x > (below + kBPanelRows - 1) / kBPanelRows) return;
+  __shared__ __attribute__((aligned(16))) double lds[panel_lds_doubles<kBPanelTPW>()];
+  potrf_panel_mfma<kBPanelTPW>(P.m, P.m, Mpool + P.M_off, P.ldm, p, blockIdx.x,
                               diagpool + P.diag_off + (long)(p / NB) * NB * NB, fail + lp,
                               minp_bits + lp, lds);
 }
@@ -763,7 +767,7 @@ void launch_bpotrf_panel(hipStream_t st, int count, int max_m, const BatchLP* lp
                          double* Mpool, double* diagpool, int p, int* fail,
                          unsigned long long* minp_bits) {
   const int below = max_m - p - NB;
-  const int gx = 1 + (below > 0 ? cdiv(below, kPanelRows) : 0);
+  const int gx = 1 + (below > 0 ? cdiv(below, kBPanelRows) : 0);
   hipLaunchKernelGGL(k_bpotrf_panel, dim3(gx, count), dim3(256), 0, st, lps, go, Mpool, diagpool,
                      p, fail, minp_bits);
 }
