@@ -245,6 +245,25 @@ lp_status lp_batch_setup(lp_batch** h, int32_t count, const int64_t* m, const in
 lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t* status,
                          int32_t* iters, int32_t* n_converged);
 
+/* One pass of the Section 3 loop body for every LP of the batch that is still
+ * running, as one iteration of lp_batch_solve: an LP whose x^T s < gap_tol
+ * stops first with LP_CONVERGED (gap_tol 0: no gap test); every other running
+ * LP takes one direction, the zero-direction test, the ratio test, the
+ * psi == 1 rule and the step.  There is no iteration limit here; LPs stopped
+ * earlier (by this call or lp_batch_solve) are left as they are.
+ * status (host, count entries, nullable) receives each LP's status after the
+ * call (LP_OK while it keeps running).  info (host, count entries, nullable)
+ * receives, per LP in the caller's order: k, the index of the direction
+ * computed in this call, or -1 when the LP took none (then only status and
+ * gap_before = gap_after, its current x^T s, are meaningful); status;
+ * gap_before and gap_after; psi (NaN after a breakdown); t and argmax (of the
+ * step taken, or undone for LP_ERR_LOST_INTERIOR; 0 and -1 otherwise);
+ * min_pivot (the smallest Cholesky pivot of the step); precision_used
+ * (LP_PREC_FP64).  Returns LP_OK unless a HIP call failed
+ * (LP_ERR_DEVICE) or h is NULL or gap_tol is negative or NaN
+ * (LP_ERR_INVALID_ARG).  Synchronises. */
+lp_status lp_batch_iterate(lp_batch* h, double gap_tol, int32_t* status, lp_iter_info* info);
+
 /* Copy the current iterates to device buffers x (sum n_i), y (sum m_i) and
  * s (sum n_i), packed contiguously in LP order (LP i's n-vector starts at
  * n_0 + ... + n_{i-1}); any may be NULL.  Stream-ordered. */

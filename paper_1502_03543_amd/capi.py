@@ -130,6 +130,7 @@ def _signatures(lib):
         "lp_batch_setup": (_st, [C.POINTER(P), C.c_int32, P, P, P, P, P, P, P, P, P, P, P,
                                  C.POINTER(lp_options), P, C.c_size_t, P]),
         "lp_batch_solve": (_st, [P, C.c_double, C.c_int32, P, P, C.POINTER(C.c_int32)]),
+        "lp_batch_iterate": (_st, [P, C.c_double, P, P]),
         "lp_batch_get_iterate": (_st, [P, P, P, P]),
         "lp_batch_backward": (_st, [P, P, P, P, P, P, P, P, P, P]),
         "lp_batch_destroy": (_st, [P]),
@@ -201,6 +202,7 @@ lp_backward = _fn("lp_backward")
 lp_batch_workspace_size = _fn("lp_batch_workspace_size")
 lp_batch_setup = _fn("lp_batch_setup")
 lp_batch_solve = _fn("lp_batch_solve")
+lp_batch_iterate = _fn("lp_batch_iterate")
 lp_batch_get_iterate = _fn("lp_batch_get_iterate")
 lp_batch_backward = _fn("lp_batch_backward")
 lp_batch_destroy = _fn("lp_batch_destroy")

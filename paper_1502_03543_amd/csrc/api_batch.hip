@@ -416,6 +416,60 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
   return LP_OK;
 }
 
+lp_status lp_batch_iterate(lp_batch* h, double gap_tol, int32_t* status, lp_iter_info* info) {
+  if (!h || !(gap_tol >= 0)) return LP_ERR_INVALID_ARG;
+  hipStream_t s = h->st;
+  BatchArgs a = h->args;
+  a.tol = gap_tol;
+  a.max_iter = INT_MAX;  // no iteration limit: the caller drives the loop
+  const int count = h->count;
+  std::vector<BatchState> before(count), after(count);
+  std::vector<unsigned long long> minp(count);
+  hipError_t e = hipMemcpyAsync(before.data(), h->state, sizeof(BatchState) * count,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) {
+    launch_batch_step(s, a, h->max_m, -1, nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(after.data(), h->state, sizeof(BatchState) * count,
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(minp.data(), a.minp, sizeof(unsigned long long) * count,
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return LP_ERR_DEVICE;
+  for (int k = 0; k < count; ++k) {
+    const int i = h->order[k];  // slot k holds the caller's LP i
+    const BatchState& B = before[k];
+    const BatchState& S = after[k];
+    h->max_iters_run = std::max(h->max_iters_run, S.iters);
+    if (status) status[i] = S.status;
+    if (!info) continue;
+    lp_iter_info& o = info[i];
+    // a step was taken when the iteration count moved, or when the step
+    // itself ended the run (a rejected step leaves the count unchanged)
+    const bool ran = B.status == LP_OK && !(S.status == LP_CONVERGED && S.iters == B.iters);
+    // psi, t and argmax belong to this call's step when it was taken or
+    // undone (LP_ERR_LOST_INTERIOR); an earlier stop leaves them stale
+    const bool stepped = ran && (S.iters == B.iters + 1 || S.status == LP_ERR_LOST_INTERIOR);
+    o.k = ran ? B.iters : -1;
+    o.status = S.status;
+    o.gap_before = B.gap;
+    o.gap_after = S.gap;
+    o.psi = ran ? S.last_psi : 0.0;
+    o.t = stepped ? S.last_t : 0.0;
+    o.argmax = stepped ? S.last_argmax : -1;
+    double mp;
+    std::memcpy(&mp, &minp[k], sizeof(double));
+    o.min_pivot = ran ? mp : 0.0;
+    o.precision_used = LP_PREC_FP64;
+    o.refine_steps = 0;
+    o.refine_resid = 0.0;
+  }
+  return LP_OK;
+}
+
 lp_status lp_batch_get_iterate(const lp_batch* h, double* x, double* y, double* s) {
   if (!h) return LP_ERR_INVALID_ARG;
   double* const* p = reinterpret_cast<double* const*>(h->bufptrs);

@@ -274,6 +274,16 @@ class Batch:
                                        C.byref(nconv)), "lp_batch_solve")
         return dict(status=np.array(stat[:]), iters=np.array(its[:]), n_converged=nconv.value)
 
+    def iterate(self, tol=0.0):
+        """One loop pass for every running LP (lp_batch_iterate).  Returns
+        (status array, list of per-LP step dicts, caller's LP order)."""
+        import numpy as np
+
+        stat = (C.c_int32 * self.count)()
+        info = (capi.lp_iter_info * self.count)()
+        capi.check(capi.lp_batch_iterate(self.h, float(tol), stat, info), "lp_batch_iterate")
+        return np.array(stat[:]), [info[i].as_dict() for i in range(self.count)]
+
     def iterates(self):
         """List of (x, y, s) numpy arrays, one per LP."""
         sn, sm = int(self.n.sum()), int(self.m.sum())

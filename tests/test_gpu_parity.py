@@ -70,6 +70,13 @@ def test_cholesky_and_solve(torch_dev, m):
     assert fo == -1
     kappa = np.linalg.cond(M)
     assert np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo) <= max(1e-13, 10 * m * U * kappa)
+    # element by element, against the scale of the entry's row (||L_i,:|| =
+    # sqrt(M_ii)): both factors are backward stable, so they differ by the
+    # conditioning times the unit roundoff
+    row = np.sqrt(np.diag(M))[:, None]
+    elt = np.abs(Lg - Lo) / row
+    assert np.all(elt <= max(1e-14, 10 * m * U * kappa)), float(elt.max())
+    assert np.all(np.triu(Lg, 1) == 0.0)
     assert np.linalg.norm(Lg @ Lg.T - M) / np.linalg.norm(M) <= 10 * m * U
     assert abs(minp - mpo) <= 1e-12 * mpo
     r = rng.standard_normal(m)
@@ -95,7 +102,8 @@ def _kappa(Mo):
     return np.linalg.cond(Mo)
 
 
-@pytest.mark.parametrize("m,n,seed", [(64, 256, 0), (100, 333, 1), (130, 517, 2)])
+@pytest.mark.parametrize("m,n,seed", [(64, 256, 0), (100, 333, 1), (130, 517, 2),
+                                      (700, 2800, 3)])
 def test_iteration_parity(torch_dev, m, n, seed):
     """Every step on the GPU's own input iterate: dy, psi, argmax, t and the
     new iterate against oracle.iterate on the same bytes."""
@@ -105,7 +113,7 @@ def test_iteration_parity(torch_dev, m, n, seed):
     print(f"iteration parity m={m} n={n} seed={seed}", flush=True)
     h = solver.LP(*_lp_tensors(torch, dev, lp), alpha=0.95)
     strict = 0
-    for k in range(60):
+    for k in range(100):
         x, y, s = (v.cpu().numpy() for v in h.iterate_values())
         if x @ s < 1e-8:
             break
@@ -141,7 +149,7 @@ def test_iteration_parity(torch_dev, m, n, seed):
 
 
 @pytest.mark.parametrize("m,n,seed", [(64, 256, 0), (64, 256, 1), (64, 256, 2), (100, 333, 3),
-                                      (130, 517, 4), (257, 1100, 5)])
+                                      (130, 517, 4), (257, 1100, 5), (1024, 4096, 6)])
 def test_solve_parity(torch_dev, m, n, seed):
     """Whole Section 3 loop to x^T s < 1e-8: same status and iteration count
     as the oracle, dual objective within 1e-9 relative."""
@@ -235,14 +243,27 @@ def test_determinism(torch_dev):
         np.testing.assert_array_equal(a, b)
 
 
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    if name.endswith(".npy"):
+        return np.load(path)
+    with open(path) as f:
+        return json.load(f)
+
+
 def test_full_size_lp2048x8192(torch_dev):
-    """The benchmark instance (m=2048, n=8192) in the benchmark's launch
-    configuration: sampled normal-matrix entries against exact dot products,
-    the first direction against the oracle on the same bytes, and the whole
-    solve through properties that hold at any size."""
+    """The benchmark instance (m=2048, n=8192, seed 0) in the benchmark's
+    launch configuration: sampled normal-matrix entries against exact dot
+    products; the first direction and the whole solve (status, K, b^T y)
+    against the oracle's, stored by tests/golden/make_golden.py; and
+    properties that hold at any size."""
     torch, dev = torch_dev
     from paper_1502_03543_amd import solver
     m, n = 2048, 8192
+    gold = _golden("lp2048x8192_seed0.json")
+    dy0 = _golden("lp2048x8192_seed0_dy0.npy")
     lp = lpgen.gen_lp(m, n, 0)
     T = _lp_tensors(torch, dev, lp)
     print("full size: normal matrix samples", flush=True)
@@ -263,16 +284,28 @@ def test_full_size_lp2048x8192(torch_dev):
     info = h.iterate()
     assert info["status"] == capi.LP_OK
     _, dyg, _ = (v.cpu().numpy() for v in h.direction())
-    it = oracle.iterate(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95)
-    rel = np.linalg.norm(dyg - it.dy) / np.linalg.norm(it.dy)
+    fd = gold["first_direction"]
+    rel = np.linalg.norm(dyg - dy0) / np.linalg.norm(dy0)
+    print(f"first dy relative difference {rel:.2e}", flush=True)
     assert rel <= 1e-10, rel
-    assert abs(info["psi"] - it.psi) <= 1e-10 * it.psi and info["argmax"] == it.argmax
+    assert abs(info["psi"] - fd["psi"]) <= 1e-10 * fd["psi"] and info["argmax"] == fd["argmax"]
     print("full size: whole solve", flush=True)
     res = h.solve(1e-8, 200, want_log=True)
-    assert res["status"] == capi.LP_CONVERGED
+    K = res["iters"] + 1
+    by = res["dual_obj"]
+    print(f"GPU: {capi.status_string(res['status'])} K={K} b^T y={by!r}; oracle: "
+          f"{gold['status']} K={gold['iters']} b^T y={gold['dual_obj']!r}", flush=True)
+    psi_g = [info["psi"]] + [e["psi"] for e in res["log"]]
+    psi_o = [e["psi"] for e in gold["log"]]
+    dpsi = [abs(a - b) / b for a, b in zip(psi_g, psi_o)]
+    print("psi relative difference per iteration:", ["%.0e" % v for v in dpsi], flush=True)
+    assert capi.status_string(res["status"]) == "LP_" + gold["status"] == "LP_CONVERGED"
+    assert K == gold["iters"], (K, gold["iters"])
+    assert abs(by - gold["dual_obj"]) <= 1e-9 * max(1.0, abs(gold["dual_obj"]))
     x, y, s = (v.cpu().numpy() for v in h.iterate_values())
     gap = x @ s
     assert gap < 1e-8 and np.all(x > 0) and np.all(s > 0)
+    assert abs(lp.b @ y - by) <= 1e-12 * max(1.0, abs(by))
     assert np.linalg.norm(lp.A @ x - lp.b) <= 1e-8 * np.linalg.norm(lp.b)
     assert np.linalg.norm(lp.A.T @ y + s - lp.c) <= 1e-11 * np.linalg.norm(lp.c)
     # c^T x - b^T y = x^T s + y^T r_p + x^T r_d: the identity holds up to the
