@@ -91,10 +91,19 @@ def test_backward_without_tape_fails(torch_dev):
 
 def test_batch_backward_differentiable_config(torch_dev):
     """64 LPs, m = 256, n = 1024, K = 30, alpha = 0.9, loss w^T x_K: the batched
-    reverse sweep against the oracle's reverse mode on the GPU's own tape for
-    4 LPs (norm-wise 1e-6 for Abar and bbar, the others reported)."""
+    reverse sweep against (1) the oracle's reverse mode on the GPU's own tape
+    for 4 LPs, norm-wise, and (2) long-double central differences of the
+    forward map (h = 1e-6 and h/2, stored by tests/golden/make_golden.py)
+    along seeded directions of A, b and c for 3 LPs."""
+    import json
+    import os
+    import sys
     torch, dev = torch_dev
     from paper_1502_03543_amd import solver
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import fd_direction
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fd_lp256x1024_K30.json")) as f:
+        fdg = json.load(f)
     K = 30
     lps = [lpgen.gen_lp(256, 1024, i) for i in range(64)]
     ws = [lpgen.loss_weights(1024, i) for i in range(64)]
@@ -107,21 +116,51 @@ def test_batch_backward_differentiable_config(torch_dev):
     g = bt.backward(torch.from_numpy(np.concatenate(ws)).to(dev))
     tapes = bt.tape(K)
     Ag = g["A"].cpu().numpy()
+    bg = g["b"].cpu().numpy()
+    cg = g["c"].cpu().numpy()
+
+    def grads(i):
+        a0 = int(bt.a_off[i])
+        return dict(A=Ag[a0:a0 + 256 * 1024].reshape(256, 1024),
+                    b=bg[bt.v_off_m[i]:bt.v_off_m[i] + 256],
+                    c=cg[bt.v_off_n[i]:bt.v_off_n[i] + 1024])
+
+    fails = []
     for i in (0, 17, 40, 63):
         lp = lps[i]
         st, go = oracle.backward(lp.A, lp.b, lp.c, 0.9, K, tapes[i], ws[i])
         assert st == oracle.CONTINUE
-        # two FP64 evaluations of the same step differ by about u kappa(M) in
-        # dy and in the solve with M; kappa(M) reaches 1e10..1e12 by step 30
-        kap = max(np.linalg.cond(oracle.iterate(lp.A, lp.b, lp.c, r[:1024], r[1024:1280],
-                                                r[1280:], 0.9).M) for r in tapes[i][-3:])
+        # condition of M at every recorded step (2-norm, from the oracle's M
+        # on the GPU's tape row), and the pivot ratio of its factor
+        kaps, pivr = [], []
+        for r in tapes[i]:
+            it = oracle.iterate(lp.A, lp.b, lp.c, r[:1024], r[1024:1280], r[1280:], 0.9)
+            kaps.append(np.linalg.cond(it.M))
+            piv = np.diag(it.L) ** 2
+            pivr.append(piv.max() / piv.min())
+        kap = max(kaps)
+        gi = grads(i)
+        ra = np.linalg.norm(gi["A"] - go["Abar"]) / np.linalg.norm(go["Abar"])
+        rb = np.linalg.norm(gi["b"] - go["bbar"]) / np.linalg.norm(go["bbar"])
+        rc = np.linalg.norm(gi["c"] - go["cbar"]) / np.linalg.norm(go["cbar"])
+        # two FP64 evaluations of the sweep differ by about u kappa(M) per
+        # solve with M; the bound takes the worst step
         tol = max(1e-6, 2 * U * kap)
-        a0 = int(bt.a_off[i])
-        Ai = Ag[a0:a0 + 256 * 1024].reshape(256, 1024)
-        bi = g["b"].cpu().numpy()[bt.v_off_m[i]:bt.v_off_m[i] + 256]
-        ci = g["c"].cpu().numpy()[bt.v_off_n[i]:bt.v_off_n[i] + 1024]
-        ra = np.linalg.norm(Ai - go["Abar"]) / np.linalg.norm(go["Abar"])
-        rb = np.linalg.norm(bi - go["bbar"]) / np.linalg.norm(go["bbar"])
-        rc = np.linalg.norm(ci - go["cbar"]) / np.linalg.norm(go["cbar"])
-        print(f"LP {i}: Abar {ra:.1e} bbar {rb:.1e} cbar {rc:.1e} (kappa {kap:.1e}, tol {tol:.1e})")
-        assert ra <= tol and rb <= tol, (i, ra, rb, tol)
+        print(f"LP {i}: Abar {ra:.2e} bbar {rb:.2e} cbar {rc:.2e}; max kappa(M) {kap:.2e} "
+              f"(u kappa {U * kap:.1e}, tol {tol:.1e}); pivot ratio max {max(pivr):.1e}",
+              flush=True)
+        if not (ra <= tol and rb <= tol and rc <= tol):
+            fails.append((i, ra, rb, rc, tol))
+    h = fdg["h"]
+    for e in fdg["entries"]:
+        i, key = e["lp"], e["key"]
+        E = fd_direction(key, i, grads(i)[key].shape)
+        an = float(np.sum(grads(i)[key] * E))
+        fd = e["fd_h"]
+        slack = max(1e-6 * abs(an), 2 * abs(e["fd_h"] - e["fd_h2"]))
+        print(f"FD LP {i} d/d{key}: adjoint {an:.10e} central difference {fd:.10e} "
+              f"(h/2: {e['fd_h2']:.10e}) |diff| {abs(an - fd):.1e} allowed {slack:.1e}",
+              flush=True)
+        if not abs(an - fd) <= slack:
+            fails.append((i, key, an, fd, slack))
+    assert not fails, fails
