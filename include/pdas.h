@@ -321,6 +321,28 @@ lp_status lp_cholesky(int64_t m, double* M, int64_t ldm, void* workspace, size_t
 lp_status lp_chol_solve(int64_t m, const double* L, int64_t ldm, const double* r, double* dy,
                         void* workspace, size_t ws_bytes, lp_stream_t stream);
 
+/* ------------------------------------------------------------------------- */
+/* Allocation-free entry point                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Largest m accepted by lp_chol_solve_noalloc. */
+#define LP_NOALLOC_MAX_M 32768
+
+/* lp_chol_solve for callers that cannot allocate device memory or supply a
+ * workspace (code under stream capture, serving loops that forbid
+ * allocation): dy = L^-T L^-1 r with the same kernels and the same result as
+ * lp_chol_solve, its scratch (about 260 KiB: the triangular solves' tickets
+ * and flags and z = L^-1 r) taken from a fixed device array that the library
+ * holds on every GPU it runs on until the process ends.  L (device,
+ * row-major lower, ldm >= m), r and dy (device m-vectors, not aliased).
+ * Errors: LP_ERR_INVALID_ARG (NULL, aliasing, ldm < m), LP_ERR_SHAPE
+ * (m < 1), LP_ERR_WORKSPACE (m > LP_NOALLOC_MAX_M), LP_ERR_DEVICE.  Calls no
+ * allocator; stream-ordered, does not synchronise.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (several
+ * streams or host threads) race and must be serialised by the caller. */
+lp_status lp_chol_solve_noalloc(int64_t m, const double* L, int64_t ldm, const double* r,
+                                double* dy, lp_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif
