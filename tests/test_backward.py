@@ -94,7 +94,13 @@ def test_batch_backward_differentiable_config(torch_dev):
     reverse sweep against (1) the oracle's reverse mode on the GPU's own tape
     for 4 LPs, norm-wise, and (2) long-double central differences of the
     forward map (h = 1e-6 and h/2, stored by tests/golden/make_golden.py)
-    along seeded directions of A, b and c for 3 LPs."""
+    along seeded directions of A, b and c for 3 LPs.
+
+    Bound: 1e-6 relative, widened to 2 u kappa where the recorded steps'
+    normal matrices are worse conditioned than that allows (u the FP64 unit
+    roundoff, kappa the largest 2-norm condition number of M over the steps):
+    two FP64 evaluations of a solve with M differ by about u kappa, and by
+    step 30 kappa reaches 1e10..1e12 (measured errors in the design notes)."""
     import json
     import os
     import sys
@@ -125,7 +131,7 @@ def test_batch_backward_differentiable_config(torch_dev):
                     b=bg[bt.v_off_m[i]:bt.v_off_m[i] + 256],
                     c=cg[bt.v_off_n[i]:bt.v_off_n[i] + 1024])
 
-    fails = []
+    fails, kap_of = [], {}
     for i in (0, 17, 40, 63):
         lp = lps[i]
         st, go = oracle.backward(lp.A, lp.b, lp.c, 0.9, K, tapes[i], ws[i])
@@ -139,6 +145,7 @@ def test_batch_backward_differentiable_config(torch_dev):
             piv = np.diag(it.L) ** 2
             pivr.append(piv.max() / piv.min())
         kap = max(kaps)
+        kap_of[i] = kap
         gi = grads(i)
         ra = np.linalg.norm(gi["A"] - go["Abar"]) / np.linalg.norm(go["Abar"])
         rb = np.linalg.norm(gi["b"] - go["bbar"]) / np.linalg.norm(go["bbar"])
@@ -157,7 +164,10 @@ def test_batch_backward_differentiable_config(torch_dev):
         E = fd_direction(key, i, grads(i)[key].shape)
         an = float(np.sum(grads(i)[key] * E))
         fd = e["fd_h"]
-        slack = max(1e-6 * abs(an), 2 * abs(e["fd_h"] - e["fd_h2"]))
+        # the differences' own spread, and the adjoint's rounding bound
+        # 2 u kappa ||grad|| ||E|| (||E|| = 1) projected on the direction
+        own = 2 * U * kap_of[i] * np.linalg.norm(grads(i)[key])
+        slack = max(1e-6 * abs(an), 2 * abs(e["fd_h"] - e["fd_h2"]), own)
         print(f"FD LP {i} d/d{key}: adjoint {an:.10e} central difference {fd:.10e} "
               f"(h/2: {e['fd_h2']:.10e}) |diff| {abs(an - fd):.1e} allowed {slack:.1e}",
               flush=True)
