@@ -12,9 +12,12 @@ Prints one JSON line: LP solves/s, plus the normal-matrix kernel's roofline
 timed on a bounded sample of the same workload.
 
 The same line carries the batched comparison (512 ragged LPs solved together
-against the single-LP FP64 solver applied LP by LP on a sample of them) and
-the reverse-mode workload (64 LPs, K = 30 steps with a tape plus the reverse
-sweep, with the oracle's forward and reverse sweep on a sample beside it).
+against the single-LP FP64 solver applied LP by LP on a sample of them), the
+reverse-mode workload (64 LPs, K = 30 steps with a tape plus the reverse
+sweep, with the oracle's forward and reverse sweep on a sample beside it) and
+the mixed-precision comparison (m=8192, n=32768: one mixed solve against one
+FP64 solve, with the FP64 Cholesky and the FP32 and FP64 normal-matrix
+kernels against their peaks).
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants]
   python bench.py --mixed-compare   # m=8192, n=32768: mixed precision vs FP64, one solve each
@@ -33,11 +36,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {
     "lp2048x8192": dict(m=2048, n=8192, seed=0, alpha=0.95, tol=1e-8,
                         desc="single LP m=2048 n=8192 FP64, Gaussian A, alpha 0.95, to gap 1e-8"),
+    "lp8192x32768": dict(m=8192, n=32768, seed=0, alpha=0.95, tol=1e-8,
+                         desc="single LP m=8192 n=32768 FP64, Gaussian A, alpha 0.95, to gap 1e-8"),
     "lp64x256": dict(m=64, n=256, seed=0, alpha=0.95, tol=1e-8,
                      desc="single LP m=64 n=256 FP64, Gaussian A, alpha 0.95, to gap 1e-8"),
 }
@@ -195,6 +201,95 @@ def adjoint_variant(lpgen, solver, capi, torch, cpu: bool) -> dict:
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"LPs 0..{ns - 1} of the {count}: oracle forward {K} steps with tape and "
                       f"reverse sweep, {dt:.2f} s"}
+    return out
+
+
+def mixed_variant(lpgen, solver, capi, torch) -> dict:
+    """m=8192, n=32768 (seed 0): one FP64 solve and one mixed-precision solve
+    from the same start to gap 1e-8, each timed whole (inputs resident, handle
+    set up, one warm-up iteration on a separate handle first), with per-phase
+    device times and the FP32 normal-matrix kernel's time on the iterations
+    that kept the FP32 factor."""
+    import numpy as np
+
+    m, n = 8192, 32768
+    dev = torch.device("cuda:0")
+    lp = lpgen.gen_lp(m, n, 0)
+    T = [torch.from_numpy(v).to(dev) for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
+    del lp
+    torch.cuda.synchronize()
+    out = {"workload": "single LP m=8192 n=32768, Gaussian A (seed 0), alpha 0.95, to gap 1e-8: "
+                       "mixed precision (FP32 normal matrix and factor, FP64 refinement and "
+                       "fallback) vs plain FP64"}
+    for prec in ("fp64", "mixed"):
+        w = solver.LP(*T, alpha=0.95, precision=prec)
+        w.iterate()
+        w.close()
+        h = solver.LP(*T, alpha=0.95, precision=prec, profile=True)
+        torch.cuda.synchronize()
+        fp32_kernel_ms, fp32_iters, prev = 0.0, 0, h.timings()
+        t0 = time.perf_counter()
+        # the loop of lp_solve, driven from here to attribute the FP32 kernel
+        # time: stop once x^T s < 1e-8 after a step (the start gap is large)
+        iters, st = 0, capi.LP_OK
+        while True:
+            info = h.iterate()
+            iters += 1
+            cur = h.timings()
+            if info["precision_used"] == capi.LP_PREC_MIXED:
+                fp32_kernel_ms += cur["normal_kernel_ms"] - prev["normal_kernel_ms"]
+                fp32_iters += 1
+            prev = cur
+            if info["status"] != capi.LP_OK:
+                st = info["status"]
+                break
+            if info["gap_after"] < 1e-8:
+                st = capi.LP_CONVERGED
+                break
+            if iters >= 300:
+                st = capi.LP_MAX_ITER
+                break
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = h.solve(1e-8, 0)  # objectives of the final iterate (no step taken)
+        tim = h.timings()
+        k = max(tim["iterations"], 1)
+        out[prec] = {
+            "status": capi.status_string(st), "iterations": iters, "seconds": dt,
+            "dual_obj": res["dual_obj"],
+            "ms_per_iteration": tim["iter_ms"] / k,
+            "normal_matrix_ms_per_iteration": tim["normal_ms"] / k,
+            "cholesky_ms_per_iteration": tim["potrf_ms"] / k,
+            "triangular_solves_ms_per_iteration": tim["trsv_ms"] / k,
+            "other_ms_per_iteration": tim["other_ms"] / k,
+        }
+        if prec == "mixed":
+            out[prec]["fp32_iterations"] = fp32_iters
+            out[prec]["fp32_normal_kernel_ms"] = fp32_kernel_ms / max(fp32_iters, 1)
+        else:
+            out[prec]["normal_kernel_ms"] = tim["normal_kernel_ms"] / max(tim["normal_launches"], 1)
+        h.close()
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    out["dual_obj_rel_diff"] = abs(out["mixed"]["dual_obj"] - out["fp64"]["dual_obj"]) / max(
+        1.0, abs(out["fp64"]["dual_obj"]))
+    f64, mx = out["fp64"], out["mixed"]
+    rl = []
+    a = syrk_flops(m, n) / (f64["normal_kernel_ms"] * 1e-3) / 1e12
+    rl.append({"kernel": "k_syrk_sk FP64 normal matrix, m=8192 n=32768", "bound": "mfma",
+               "achieved": a, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+               "frac": a / PEAK_FP64_MFMA_TFLOPS})
+    a = potrf_flops(m) / (f64["cholesky_ms_per_iteration"] * 1e-3) / 1e12
+    rl.append({"kernel": "FP64 Cholesky (all launches of one factorization), m=8192",
+               "bound": "mfma", "achieved": a, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+               "frac": a / PEAK_FP64_MFMA_TFLOPS})
+    if mx.get("fp32_iterations"):
+        a = syrk_flops(m, n) / (mx["fp32_normal_kernel_ms"] * 1e-3) / 1e12
+        rl.append({"kernel": "FP32 normal matrix (mixed precision), m=8192 n=32768",
+                   "bound": "mfma", "achieved": a, "peak": PEAK_FP32_MFMA_TFLOPS,
+                   "unit": "TFLOP/s", "frac": a / PEAK_FP32_MFMA_TFLOPS})
+    out["rooflines"] = rl
+    del T
+    torch.cuda.empty_cache()
     return out
 
 
@@ -374,10 +469,18 @@ def main():
     }
     for h in handles:
         h.close()
+    a = potrf_flops(m) / (tot["potrf_ms"] / tot["iterations"] * 1e-3) / 1e12
+    out["rooflines_other"] = [{
+        "kernel": f"FP64 Cholesky (all launches of one factorization), m={m}", "bound": "mfma",
+        "achieved": a, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+        "frac": a / PEAK_FP64_MFMA_TFLOPS,
+        "algorithmic_flops_per_factorization": potrf_flops(m),
+        "avg_ms": tot["potrf_ms"] / tot["iterations"]}]
     if not args.no_variants:
         out["variants"] = {
             "batched": batch_variant(lpgen, solver, capi, torch),
             "adjoint": adjoint_variant(lpgen, solver, capi, torch, not args.no_cpu_baseline),
+            "mixed": mixed_variant(lpgen, solver, capi, torch),
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lp, K, args.cpu_sample_iters)
