@@ -2,12 +2,15 @@
 // names Cholesky as the usual solver for the symmetric positive definite
 // A D A^T).  Row-major lower storage, panel width kTB = 64.
 //
-// FP64, per panel p:
+// FP64, per panel p (panels grouped by four, see launch_potrf_f64):
 //   1. k_chol_step: the panel step (potrf_panel_mfma: A11 and the panel rows
 //      on the matrix cores, L11 to a side buffer, the rows below solved in
-//      place) in its first workgroups and, in the others, the previous
-//      panel's update of the trailing columns from p + 64 on;
-//   2. k_chol_col0: panel p applied to the next panel's 64 columns.
+//      place) in its first workgroups and, in the others, trailing updates
+//      of the columns from p + 64 on: the previous panel's inside the group
+//      (K = 64) and the previous group's beyond it (K = 256), on 64 x 64
+//      tiles of the 16 x 16 x 4 FP64 matrix instruction;
+//   2. k_chol_col0: the next panel's 64 columns updated with panel p, or
+//      with the whole group when the next panel starts a new group.
 // FP32 (mixed precision): potrf_panel_body, one wavefront factoring A11 with
 // the panel rows solved by the other three, then the FP32 trailing update.
 // Rows below the last column (mr > mc) are carried through every step like
@@ -604,7 +607,7 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
 }
 
 // FP64 panel rows per workgroup (16-row tiles per wavefront 1..3)
-constexpr int kPanelTPW = 2;
+constexpr int kPanelTPW = 1;
 constexpr int kPanelRows = PanelShape<kPanelTPW>::rows;
 
 __global__ __launch_bounds__(256) void k_potrf_panel_f64(int mr, int mc, double* __restrict__ M,
@@ -617,23 +620,169 @@ __global__ __launch_bounds__(256) void k_potrf_panel_f64(int mr, int mc, double*
                               reinterpret_cast<unsigned long long*>(&info->min_pivot), lds);
 }
 
-// The fused Cholesky step at column p.  Workgroups 0 .. npw_need - 1 run the
-// panel step; workgroups from npw (a multiple of 8, so that the update's
-// tile order stays XCD-aware) apply the previous panel (columns p - NB ..
-// p - 1) to the trailing columns from p + NB on.  The two write disjoint
-// parts of M (the panel its own columns, the update the columns beyond), and
-// the previous panel's contribution to columns p .. p + NB - 1 was applied
-// by its own column update (k_chol_col0) before this launch, so the panel
-// factorisation no longer waits for the whole trailing update.
-constexpr int kStepLds = panel_lds_doubles<kPanelTPW>() > 2 * syrk_tile_lds2<8, 32>()
-                             ? panel_lds_doubles<kPanelTPW>()
-                             : 2 * syrk_tile_lds2<8, 32>();
+// ---------------------------------------------------------------------------
+// Trailing updates:
+//   C[i][j] -= sum_{k < K} X[i][k] X[j][k]
+// over a lower trapezoid: rows [0, mm) and columns [0, ncols) of C (j <= i),
+// with X the factor's rows at the same offsets (K = 64 for one panel, 64 G
+// for a group of G panels).  One BM x BM tile per workgroup on the
+// 16 x 16 x 4 FP64 matrix instruction (lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; slot v of the result is D[l / 16 + 4 v][l % 16]):
+// 2 x 2 wavefronts of BM/2 x BM/2 (blocks of 16 x 16), operands
+// through double-buffered LDS in stages of 16 along K with rows padded to 18
+// doubles.  The accumulators start from the C values (loaded beside the
+// first stage, so their latency overlaps it) and the row operand is staged
+// negated, so the matrix instructions leave C - X X^T directly.
+// BM = 128 where the updates are large (fewer, longer tiles: each operand
+// row is reused by twice the columns); BM = 64 where they must finish within
+// one panel step (twice the workgroups of a quarter of the work each)
+constexpr int kUpKC = 16, kUpLS = kUpKC + 2;
+template <int BM>
+constexpr int up_lds_doubles() {
+  return 2 * 2 * BM * kUpLS;
+}
 
+struct CholUpd {
+  int c0;      // C and the row operand start at row and column c0 of M
+  int ncols;   // columns c0 .. c0 + ncols - 1 are updated
+  int kcol;    // factor columns kcol .. kcol + K - 1 are applied
+  int K;       // a multiple of 32
+  int nrt;     // row tiles: cdiv(mr - c0, BM)
+  int ntiles;  // tiles of the trapezoid
+};
+
+__host__ __device__ inline int trap_tiles(int nrt, int nct) {
+  return nct * nrt - nct * (nct - 1) / 2;
+}
+
+// Tile t of the trapezoid, column by column: column tj holds row tiles
+// tj .. nrt - 1.
+__device__ inline void trap_coords(int t, int nrt, int& ti, int& tj) {
+  tj = 0;
+  while (t >= nrt - tj) {
+    t -= nrt - tj;
+    ++tj;
+  }
+  ti = tj + t;
+}
+
+template <int BM>
+__device__ __forceinline__ void chol_update_tile(int mr, const CholUpd& u, double* __restrict__ M,
+                                                 long ld, int t, double* __restrict__ lds) {
+  typedef double upd4 __attribute__((ext_vector_type(4)));
+  constexpr int PPR = kUpKC / 2;              // element pairs per row per stage
+  constexpr int PAIRS = BM * PPR / 256;       // pairs per thread per operand
+  constexpr int WB = BM / 2;                  // wavefront block side
+  constexpr int NB4 = WB / 16;                // 16 x 16 blocks per wavefront side
+  int ti, tj;
+  trap_coords(t, u.nrt, ti, tj);
+  const int mm = mr - u.c0;
+  const int row0 = ti * BM, col0 = tj * BM;
+  const double* X = M + (long)u.c0 * ld + u.kcol;
+  double* C = M + (long)u.c0 * ld + u.c0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr0 = (wv >> 1) * WB, wc0 = (wv & 1) * WB;
+  // a wavefront whose block lies above the diagonal of a diagonal tile idles
+  const bool active = !(ti == tj && wr0 + WB <= wc0);
+  upd4 acc[NB4][NB4];
+#pragma unroll
+  for (int r = 0; r < NB4; ++r)
+#pragma unroll
+    for (int c = 0; c < NB4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = min(row0 + wr0 + 16 * r + lk + 4 * v, mm - 1);
+        const int gc = min(col0 + wc0 + 16 * c + li, gr);
+        acc[r][c][v] = active ? C[(long)gr * ld + gc] : 0.0;
+      }
+  double(*buf)[2][BM * kUpLS] = reinterpret_cast<double(*)[2][BM * kUpLS]>(lds);
+  double2 pa[PAIRS], pb[PAIRS];
+  // every load address is clamped into the matrix; rows outside the tile
+  // are zeroed when staged (K is a multiple of the stage length)
+  auto gload = [&](int st) {
+#pragma unroll
+    for (int it = 0; it < PAIRS; ++it) {
+      const int q = tid + 256 * it;
+      const int row = q / PPR, k = st * kUpKC + 2 * (q % PPR);
+      const long ra = min(row0 + row, mm - 1), rb = min(col0 + row, mm - 1);
+      pa[it] = *reinterpret_cast<const double2*>(X + ra * ld + k);
+      pb[it] = *reinterpret_cast<const double2*>(X + rb * ld + k);
+    }
+  };
+  auto sstore = [&](int b) {
+#pragma unroll
+    for (int it = 0; it < PAIRS; ++it) {
+      const int q = tid + 256 * it;
+      const int row = q / PPR, kk = 2 * (q % PPR);
+      // element-wise selects (a select of whole vectors went through memory)
+      const bool va = row0 + row < mm, vb = col0 + row < mm;
+      double2 sa, sb;
+      sa.x = va ? -pa[it].x : 0.0;
+      sa.y = va ? -pa[it].y : 0.0;
+      sb.x = vb ? pb[it].x : 0.0;
+      sb.y = vb ? pb[it].y : 0.0;
+      *reinterpret_cast<double2*>(&buf[b][0][row * kUpLS + kk]) = sa;
+      *reinterpret_cast<double2*>(&buf[b][1][row * kUpLS + kk]) = sb;
+    }
+  };
+  const int nst = u.K / kUpKC;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) gload(st + 1);
+    if (active) {
+      const double* la = buf[cur][0];
+      const double* lb = buf[cur][1];
+#pragma unroll
+      for (int ks = 0; ks < kUpKC / 4; ++ks) {
+        double a[NB4], b[NB4];
+#pragma unroll
+        for (int r = 0; r < NB4; ++r) a[r] = la[(wr0 + 16 * r + li) * kUpLS + 4 * ks + lk];
+#pragma unroll
+        for (int c = 0; c < NB4; ++c) b[c] = lb[(wc0 + 16 * c + li) * kUpLS + 4 * ks + lk];
+#pragma unroll
+        for (int r = 0; r < NB4; ++r)
+#pragma unroll
+          for (int c = 0; c < NB4; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
+      }
+    }
+    if (st + 1 < nst) sstore(cur ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int r = 0; r < NB4; ++r)
+#pragma unroll
+    for (int c = 0; c < NB4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
+        if (gr < mm && gc <= gr && gc < u.ncols) C[(long)gr * ld + gc] = acc[r][c][v];
+      }
+}
+
+// The fused Cholesky step at column p.  Workgroups 0 .. npw_need - 1 run the
+// panel step; workgroups from npw (a multiple of 8, so that the tile order
+// stays XCD-aware) run the tiles of up to two trailing updates (u1, then
+// u2) that the grouped schedule places beside this panel.  The panel writes
+// columns p .. p + 63; the updates write columns from p + 64 on and read
+// only finished factor columns, so nothing in one launch races.
+template <int BM>
+constexpr int step_lds_doubles() {
+  return panel_lds_doubles<kPanelTPW>() > up_lds_doubles<BM>() ? panel_lds_doubles<kPanelTPW>()
+                                                               : up_lds_doubles<BM>();
+}
+
+template <int BM>
 __global__ __launch_bounds__(256) void k_chol_step(int mr, int mc, double* __restrict__ M, long ld,
                                                    int p, double* __restrict__ diag,
                                                    DevInfo* info, int npw_need, int npw,
-                                                   int ntiles, int per_xcd) {
-  __shared__ __attribute__((aligned(16))) double lds[kStepLds];
+                                                   CholUpd u1, CholUpd u2, int per_xcd) {
+  __shared__ __attribute__((aligned(16))) double lds[step_lds_doubles<BM>()];
   const int b = blockIdx.x;
   if (b < npw) {
     if (b >= npw_need) return;
@@ -644,27 +793,26 @@ __global__ __launch_bounds__(256) void k_chol_step(int mr, int mc, double* __res
   }
   const int bb = b - npw;
   const int t = (bb & 7) * per_xcd + (bb >> 3);
-  if (t >= ntiles) return;
-  const int q = p + NB;
-  syrk_f64_tile<8, 2, 32, false, true>(mr - q, NB, M + (long)q * ld + (p - NB), ld, nullptr,
-                                       M + (long)q * ld + q, ld, 1, t, ntiles, 0, 1, NB, nullptr,
-                                       reinterpret_cast<double2*>(lds));
+  if (t < u1.ntiles) chol_update_tile<BM>(mr, u1, M, ld, t, lds);
+  else if (t - u1.ntiles < u2.ntiles) chol_update_tile<BM>(mr, u2, M, ld, t - u1.ntiles, lds);
 }
 
-// Update of the next panel's columns p + NB .. p + 2 NB - 1 (all rows from
-// p + NB) with panel p: the first two 32-wide tile columns of the trailing
-// update.  This update sits on the critical path between two panels, so it
-// uses 32 x 32 tiles: four times the workgroups of 64 x 64 tiles, each with
-// a quarter of the work.  Workgroup b takes tile (0, 0) for b = 0, else
-// ((b + 1) / 2, (b + 1) % 2).
+// Update of the next panel's columns q .. q + NB - 1 (all rows from q) with
+// the factor columns kcol .. kcol + K - 1 (K = 64: the panel just factored;
+// K = 256: the group of four just finished): the first two 32-wide tile
+// columns of that update.  This update sits on the critical path between two
+// panels, so it uses 32 x 32 tiles: four times the workgroups of 64 x 64
+// tiles, each with a quarter of the work.  Workgroup b takes tile (0, 0) for
+// b = 0, else ((b + 1) / 2, (b + 1) % 2).
 constexpr int kCol0BM = 32;
-__global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ M, long ld, int p) {
+__global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ M, long ld, int q,
+                                                   int kcol, int K) {
   __shared__ double2 lds2[syrk_tile_lds2<4, 32>()];
-  const int q = p + NB, b = blockIdx.x;
+  const int b = blockIdx.x;
   const int ti = (b + 1) / 2, tj = b == 0 ? 0 : (b + 1) % 2;
-  syrk_f64_tile<4, 1, 32, false, true>(mr - q, NB, M + (long)q * ld + p, ld, nullptr,
+  syrk_f64_tile<4, 1, 32, false, true>(mr - q, K, M + (long)q * ld + kcol, ld, nullptr,
                                        M + (long)q * ld + q, ld, 1, ti * (ti + 1) / 2 + tj, 0, 0,
-                                       1, NB, nullptr, lds2);
+                                       1, K, nullptr, lds2);
 }
 
 __global__ __launch_bounds__(256) void k_potrf_panel_f32(int mr, int mc, float* __restrict__ M,
@@ -727,24 +875,81 @@ __global__ __launch_bounds__(256) void k_bdiag_to_m(const BatchLP* __restrict__ 
 
 }  // namespace
 
+// Right-looking schedule over panels of NB = 64 columns, optionally grouped
+// by G panels.  With G = 1 every step applies the previous panel to all
+// later columns (K = 64).  With G > 1 a panel's update of the columns inside
+// its own group is applied at once (K = 64); its update of the columns
+// beyond the group is deferred and applied with the rest of the group as one
+// K = 64 G update, so the trailing matrix is read and written once per
+// group instead of once per panel.  For panel k = G g + j at column p (group
+// columns gs .. ge):
+//   step launch k: the panel, and beside it
+//     j >= 1: panel k - 1 on columns [p + 64, ge)                (K = 64)
+//     g >= 1: group g - 1 on columns [p + 64, ge)   when j = 0,  (K = 64 G)
+//             or on part j of G - 1 parts of [ge, mc) when j >= 1
+//             (with G = 1: on [p + 64, mc));
+//   then a column update of the next panel's 64 columns: panel k (K = 64)
+//   inside the group, or group g (K = 64 G) when the next panel starts the
+//   next group.
+// Every update reads finished factor columns only and no two parts of one
+// launch write the same columns; each panel's columns have received every
+// earlier panel's contribution when its step starts.
+namespace {
+constexpr int kCholGroupMinM = 4096;
+CholUpd make_upd(int bm, int mr, int c0, int c1, int kcol, int K) {
+  CholUpd u{};
+  u.c0 = c0;
+  u.ncols = c1 - c0;
+  u.kcol = kcol;
+  u.K = K;
+  u.nrt = mr > c0 ? cdiv(mr - c0, bm) : 0;
+  u.ntiles = (u.ncols > 0 && u.nrt > 0) ? trap_tiles(u.nrt, cdiv(u.ncols, bm)) : 0;
+  return u;
+}
+}  // namespace
+
 void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInfo* info,
                       double* diag) {
+  // grouping pays where the trailing update is bound by its traffic (large
+  // m); below that the per-panel update hides behind the panel itself
+  const bool big = mc >= kCholGroupMinM;
+  const int G = big ? 4 : 1, GW = G * NB, bm = big ? 128 : 64;
   for (int p = 0; p < mc; p += NB) {
+    const int k = p / NB, g = k / G, j = k % G;
+    const int gs = g * GW, ge = gs + GW < mc ? gs + GW : mc;
     const int nbe = (mc - p) < NB ? (mc - p) : NB;
     const int npw_need = 1 + cdiv(mr - p - nbe, kPanelRows);
-    // the previous panel's update of the columns from p + NB on rides along
-    int ntiles = 0, per_xcd = 0;
-    if (p > 0 && mr - (p + NB) > 0) {
-      const int nt = cdiv(mr - (p + NB), 64);
-      ntiles = nt * (nt + 1) / 2;
-      per_xcd = cdiv(ntiles, 8);
+    const CholUpd none = make_upd(bm, mr, 0, 0, 0, NB);
+    CholUpd u1 = none, u2 = none;
+    if (j >= 1) u1 = make_upd(bm, mr, p + NB, ge, p - NB, NB);
+    if (g >= 1) {
+      if (G == 1) {
+        u2 = make_upd(bm, mr, p + NB, mc, gs - GW, GW);
+      } else if (j == 0) {
+        u2 = make_upd(bm, mr, p + NB, ge, gs - GW, GW);
+      } else {
+        // part j of the later columns, in whole 64-column tiles
+        const int ntc = cdiv(mc - ge, NB);
+        const int a = ge + NB * ((ntc * (j - 1)) / (G - 1));
+        const int b = j == G - 1 ? mc : ge + NB * ((ntc * j) / (G - 1));
+        if (b > a) u2 = make_upd(bm, mr, a, b, gs - GW, GW);
+      }
     }
+    const int ntiles = u1.ntiles + u2.ntiles;
+    const int per_xcd = cdiv(ntiles, 8);
     const int npw = ntiles ? cdiv(npw_need, 8) * 8 : npw_need;
-    hipLaunchKernelGGL(k_chol_step, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M, ld, p,
-                       diag, info, npw_need, npw, ntiles, per_xcd);
-    if (p + NB < mc)
-      hipLaunchKernelGGL(k_chol_col0, dim3(2 * cdiv(mr - (p + NB), kCol0BM) - 1), dim3(256), 0, st,
-                         mr, M, ld, p);
+    if (big)
+      hipLaunchKernelGGL(k_chol_step<128>, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M,
+                         ld, p, diag, info, npw_need, npw, u1, u2, per_xcd);
+    else
+      hipLaunchKernelGGL(k_chol_step<64>, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M,
+                         ld, p, diag, info, npw_need, npw, u1, u2, per_xcd);
+    const int q = p + NB;
+    if (q < mc) {
+      const bool group_end = (q == ge);
+      hipLaunchKernelGGL(k_chol_col0, dim3(2 * cdiv(mr - q, kCol0BM) - 1), dim3(256), 0, st, mr,
+                         M, ld, q, group_end ? gs : p, group_end ? GW : NB);
+    }
   }
   hipLaunchKernelGGL(k_diag_to_m<double>, dim3(cdiv(mc, NB)), dim3(256), 0, st, mc, M, ld, diag);
 }

@@ -41,7 +41,7 @@ def _run(exe, *args, timeout=600):
     return p.stdout
 
 
-@pytest.mark.parametrize("m", [40, 64, 100, 150, 300])
+@pytest.mark.parametrize("m", [40, 64, 100, 150, 300, 700, 1100])
 def test_emulated_cholesky_with_fused_forward_solve(emu, m):
     r = json.loads(_run(emu, "chol", m).strip().splitlines()[-1])
     assert r["fail"] == -1
