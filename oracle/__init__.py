@@ -61,6 +61,21 @@ class _Log(C.Structure):
     ]
 
 
+class _PCOut(C.Structure):
+    _fields_ = [
+        ("dx_aff", _dp), ("dy_aff", _dp), ("ds_aff", _dp), ("dx", _dp), ("dy", _dp),
+        ("ds", _dp), ("rhs_aff", _dp), ("rhs", _dp),
+        ("gap", C.c_double), ("mu", C.c_double), ("mu_aff", C.c_double), ("sigma", C.c_double),
+        ("alpha_aff_p", C.c_double), ("alpha_aff_d", C.c_double), ("alpha_p", C.c_double),
+        ("alpha_d", C.c_double), ("min_pivot", C.c_double), ("fail_col", C.c_longlong),
+    ]
+
+
+class _PCLog(C.Structure):
+    _fields_ = [("gap", C.c_double), ("sigma", C.c_double), ("alpha_p", C.c_double),
+                ("alpha_d", C.c_double), ("min_pivot", C.c_double)]
+
+
 _libs: dict = {}
 
 
@@ -84,6 +99,11 @@ def _bind(lib):
     lib.orc_cholesky.restype = C.c_long
     lib.orc_cholesky_solve.argtypes = [L, P, P, P]
     lib.orc_cholesky_solve.restype = None
+    lib.orc_pc_iterate.argtypes = [L, L, P, P, P, P, P, P, D, C.POINTER(_PCOut)]
+    lib.orc_pc_iterate.restype = I
+    lib.orc_pc_solve.argtypes = [L, L, P, P, P, P, P, P, D, D, I, C.POINTER(I),
+                                 C.POINTER(_PCLog)]
+    lib.orc_pc_solve.restype = I
     lib.orc_num_threads.restype = I
     lib.orc_real_bytes.restype = I
     return lib
@@ -272,3 +292,68 @@ def cholesky_solve(L, r, precision="f64"):
     w = np.zeros(m)
     _lib(precision).orc_cholesky_solve(m, _p(L), _p(r), _p(w))
     return w
+
+
+@dataclass
+class PCResult:
+    status: int
+    x: np.ndarray
+    y: np.ndarray
+    s: np.ndarray
+    dx_aff: np.ndarray
+    dy_aff: np.ndarray
+    ds_aff: np.ndarray
+    dx: np.ndarray
+    dy: np.ndarray
+    ds: np.ndarray
+    rhs_aff: np.ndarray
+    rhs: np.ndarray
+    gap: float
+    mu: float
+    mu_aff: float
+    sigma: float
+    alpha_aff_p: float
+    alpha_aff_d: float
+    alpha_p: float
+    alpha_d: float
+    min_pivot: float
+    fail_col: int
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES[self.status]
+
+
+def pc_iterate(A, b, c, x, y, s, eta=0.95, precision="f64") -> PCResult:
+    """One predictor-corrector (Mehrotra) iteration from (x, y, s)."""
+    A, b, c = _f64(A), _f64(b), _f64(c)
+    x, y, s = _f64(x).copy(), _f64(y).copy(), _f64(s).copy()
+    m, n = A.shape
+    bufs = {k: np.full(sz, np.nan) for k, sz in
+            dict(dx_aff=n, dy_aff=m, ds_aff=n, dx=n, dy=m, ds=n, rhs_aff=m, rhs=m).items()}
+    out = _PCOut(**{k: _p(v) for k, v in bufs.items()})
+    st = _lib(precision).orc_pc_iterate(m, n, _p(A), _p(b), _p(c), _p(x), _p(y), _p(s),
+                                        float(eta), C.byref(out))
+    sc = {k: getattr(out, k) for k in ("gap", "mu", "mu_aff", "sigma", "alpha_aff_p",
+                                      "alpha_aff_d", "alpha_p", "alpha_d", "min_pivot")}
+    return PCResult(status=st, x=x, y=y, s=s, fail_col=out.fail_col, **sc, **bufs)
+
+
+def pc_solve(A, b, c, x0, y0, s0, eta=0.95, gap_tol=1e-8, max_iter=200,
+             precision="f64") -> SolveResult:
+    """The predictor-corrector loop, stopping on x^T s < gap_tol or after
+    max_iter steps; log entries hold gap, sigma, alpha_p, alpha_d, min_pivot."""
+    A, b, c = _f64(A), _f64(b), _f64(c)
+    x, y, s = _f64(x0).copy(), _f64(y0).copy(), _f64(s0).copy()
+    m, n = A.shape
+    logs = (_PCLog * max(max_iter, 1))()
+    iters = C.c_int(0)
+    st = _lib(precision).orc_pc_solve(m, n, _p(A), _p(b), _p(c), _p(x), _p(y), _p(s),
+                                      float(eta), float(gap_tol), int(max_iter),
+                                      C.byref(iters), logs)
+    k = iters.value
+    nlog = min(k + (1 if st in (ERR_BREAKDOWN, ERR_NONPOS_PSI, ERR_LOST_INTERIOR,
+                                OPTIMAL_ZERO_DIR) else 0), max_iter)
+    log = [dict(gap=logs[i].gap, sigma=logs[i].sigma, alpha_p=logs[i].alpha_p,
+                alpha_d=logs[i].alpha_d, min_pivot=logs[i].min_pivot) for i in range(nlog)]
+    return SolveResult(status=st, iters=k, x=x, y=y, s=s, log=log)

@@ -12,7 +12,9 @@
  *   - the outer loop: Section 3, Algorithm "Primal-Dual Affine Scaling";
  *   - the reduction to normal equations (ADA^T) dy = ... with D = S^-1 X:
  *     Section 5, equation (bigsystem2) and the component formulas under it;
- *   - Cholesky of ADA^T: Section 5.1 (named there as the usual method).
+ *   - Cholesky of ADA^T: Section 5.1 (named there as the usual method);
+ *   - the predictor-corrector variant at the end of this file: Mehrotra's
+ *     method, which Section 4 (previous work) cites, on the same system.
  *
  * Readings taken where the paper is silent or garbled (each listed in the
  * design notes of the repository):
@@ -805,4 +807,280 @@ void orc_cholesky_solve(long m, const double* L, const double* r, double* w) {
   cholesky_solve(m, Lr, rr, wr);
   store(w, wr, m);
   free(Lr); free(rr); free(wr);
+}
+
+/* ------------------------------------------------------------------ */
+/* Predictor-corrector variant (Mehrotra)                             */
+/* ------------------------------------------------------------------ */
+/*
+ * The paper's Section 4 (previous work) cites Mehrotra's primal-dual method
+ * as the second-order, centred refinement of the affine-scaling direction.
+ * It is a different method from the Section 3 algorithm; this is its
+ * published definition (Mehrotra, SIAM J. Optim. 2(4), 1992; as stated in
+ * S. J. Wright, Primal-Dual Interior-Point Methods, SIAM 1997, ch. 10),
+ * written out on the same Newton system (bigsystem) and the same Section 5
+ * reduction, one factorization per iteration:
+ *
+ *   predictor: the Section 3 (affine-scaling) direction, third right-hand
+ *              side r_c = -X S e;
+ *   step to the boundary, primal and dual apart:
+ *              a_max_p = min over dx_j < 0 of -x_j/dx_j (inf if none),
+ *              a_aff_p = min(1, a_max_p), and a_aff_d the same with s, ds;
+ *   centring:  mu = x^T s / n,
+ *              mu_aff = (x + a_aff_p dx_aff)^T (s + a_aff_d ds_aff) / n,
+ *              sigma = (mu_aff / mu)^3;
+ *   corrector: the same system with r_c = -X S e - dX_aff dS_aff e
+ *              + sigma mu e;
+ *   step:      a_p = min(1, eta a_max_p), a_d = min(1, eta a_max_d) for the
+ *              corrector direction; x += a_p dx, y += a_d dy, s += a_d ds.
+ *
+ * With D = S^-1 X and the residuals r_p = b - A x, r_d = c - A^T y - s,
+ * eliminating dx and ds from (A dx = r_p, A^T dy + ds = r_d,
+ * S dx + X ds = r_c) gives
+ *   (A D A^T) dy = b + A (d o r_d - x - r_c / s),
+ *   ds = r_d - A^T dy,   dx = r_c / s - d o ds;
+ * for r_c = -X S e this is the Section 5 residual-form system (R1).
+ */
+
+typedef struct {
+  double* dx_aff;  /* n, predictor direction (nullable) */
+  double* dy_aff;  /* m */
+  double* ds_aff;  /* n */
+  double* dx;      /* n, corrector direction (nullable) */
+  double* dy;      /* m */
+  double* ds;      /* n */
+  double* rhs_aff; /* m, right-hand sides of the two reduced solves */
+  double* rhs;     /* m */
+  double gap, mu, mu_aff, sigma;
+  double alpha_aff_p, alpha_aff_d, alpha_p, alpha_d;
+  double min_pivot;
+  long long fail_col;
+} orc_pc_out;
+
+typedef struct {
+  double gap;      /* before the step */
+  double sigma;
+  double alpha_p;
+  double alpha_d;
+  double min_pivot;
+} orc_pc_log;
+
+/* Largest step in [0, inf) keeping v + a dv >= 0: min over dv_j < 0 of
+ * -v_j/dv_j, +inf when no component decreases. */
+static real step_to_boundary(long n, const real* v, const real* dv) {
+  real a = INFINITY;
+  for (long j = 0; j < n; ++j)
+    if (dv[j] < 0) {
+      real r = -v[j] / dv[j];
+      if (r < a) a = r;
+    }
+  return a;
+}
+
+/* Reduced solve for third right-hand side rc (n): dy, ds, dx into S (uses
+ * the factor S->L and the dual residual S->rd already formed); rhs_out
+ * receives the reduced right-hand side. */
+static void pc_direction(state* S, const real* rc, real* rhs_out, real* dx, real* dy,
+                         real* ds) {
+  const long m = S->m, n = S->n;
+  real* t = S->g;
+  for (long j = 0; j < n; ++j) t[j] = S->d[j] * S->rd[j] - S->x[j] - rc[j] / S->s[j];
+  a_times(m, n, S->A, t, rhs_out);
+  for (long i = 0; i < m; ++i) rhs_out[i] = S->b[i] + rhs_out[i];
+  cholesky_solve(m, S->L, rhs_out, dy);
+  at_times(m, n, S->A, dy, S->g);
+  for (long j = 0; j < n; ++j) ds[j] = S->rd[j] - S->g[j];
+  for (long j = 0; j < n; ++j) dx[j] = rc[j] / S->s[j] - S->d[j] * ds[j];
+}
+
+typedef struct {
+  real gap, mu, mu_aff, sigma, a_aff_p, a_aff_d, a_p, a_d, min_pivot;
+  long fail_col;
+} pc_info;
+
+/* One predictor-corrector iteration on S; aux holds 3n + 2m + n reals for
+ * the predictor direction, the corrector right-hand side and r_c. */
+static int pc_iterate_state(state* S, real eta, real* aux, real* rhs_aff, pc_info* info) {
+  const long m = S->m, n = S->n;
+  real* dxa = aux;
+  real* dya = aux + n;
+  real* dsa = aux + n + m;
+  real* rc = aux + 2 * n + m;
+  info->fail_col = -1;
+  info->sigma = NAN;
+  info->a_p = info->a_d = NAN;
+  info->min_pivot = NAN;
+  info->gap = dot(n, S->x, S->s);
+  info->mu = info->gap / (real)n;
+
+  /* residual r_d = c - A^T y - s and D = S^-1 X (Section 5) */
+  at_times(m, n, S->A, S->y, S->g);
+  for (long j = 0; j < n; ++j) {
+    const real aty = S->g[j];
+    S->rd[j] = S->c[j] - aty - S->s[j];
+  }
+  for (long j = 0; j < n; ++j) {
+    const real xj = S->x[j], sj = S->s[j];
+    S->d[j] = xj / sj;
+  }
+
+  /* one normal matrix and one factor serve both solves */
+  normal_matrix(m, n, S->A, S->d, S->M);
+  long fail = cholesky(m, S->M, S->L, &info->min_pivot);
+  if (fail >= 0) {
+    info->fail_col = fail;
+    return ORC_ERR_BREAKDOWN;
+  }
+
+  /* predictor: r_c = -X S e */
+  for (long j = 0; j < n; ++j) rc[j] = -S->x[j] * S->s[j];
+  pc_direction(S, rc, rhs_aff, dxa, dya, dsa);
+  real ap = step_to_boundary(n, S->x, dxa), ad = step_to_boundary(n, S->s, dsa);
+  info->a_aff_p = ap < 1 ? ap : (real)1;
+  info->a_aff_d = ad < 1 ? ad : (real)1;
+  real acc = 0;
+  for (long j = 0; j < n; ++j)
+    acc += (S->x[j] + info->a_aff_p * dxa[j]) * (S->s[j] + info->a_aff_d * dsa[j]);
+  info->mu_aff = acc / (real)n;
+  real q = info->mu_aff / info->mu;
+  info->sigma = q * q * q;
+
+  /* corrector: r_c = -X S e - dX_aff dS_aff e + sigma mu e */
+  for (long j = 0; j < n; ++j)
+    rc[j] = -S->x[j] * S->s[j] - dxa[j] * dsa[j] + info->sigma * info->mu;
+  pc_direction(S, rc, S->rhs, S->dx, S->dy, S->ds);
+
+  {
+    int zero = 1;
+    for (long j = 0; j < n && zero; ++j)
+      if (S->dx[j] != 0 || S->ds[j] != 0) zero = 0;
+    for (long i = 0; i < m && zero; ++i)
+      if (S->dy[i] != 0) zero = 0;
+    if (zero) return ORC_OPTIMAL_ZERO_DIR;
+  }
+
+  real mp = step_to_boundary(n, S->x, S->dx), md = step_to_boundary(n, S->s, S->ds);
+  info->a_p = eta * mp < 1 ? eta * mp : (real)1;
+  info->a_d = eta * md < 1 ? eta * md : (real)1;
+  if (!(info->a_p > 0) || !(info->a_d > 0) || !isfinite(info->a_p) || !isfinite(info->a_d))
+    return ORC_ERR_NONPOS_PSI;
+  for (long j = 0; j < n; ++j) S->x[j] = S->x[j] + info->a_p * S->dx[j];
+  for (long i = 0; i < m; ++i) S->y[i] = S->y[i] + info->a_d * S->dy[i];
+  for (long j = 0; j < n; ++j) S->s[j] = S->s[j] + info->a_d * S->ds[j];
+  for (long j = 0; j < n; ++j)
+    if (!(S->x[j] > 0) || !(S->s[j] > 0)) return ORC_ERR_LOST_INTERIOR;
+  return ORC_CONTINUE;
+}
+
+/* One predictor-corrector iteration from (x, y, s), updated in place
+ * (eta in (0, 1): the fraction of the step to the boundary). */
+int orc_pc_iterate(long m, long n, const double* A, const double* b, const double* c,
+                   double* x, double* y, double* s, double eta, orc_pc_out* out) {
+  int st = validate(m, n, A, b, c, x, y, s, eta);
+  if (st != ORC_CONTINUE) return st;
+  state S;
+  if (!state_alloc(&S, m, n)) return ORC_ERR_INVALID_ARG;
+  real* aux = malloc(sizeof(real) * (size_t)(3 * n + m));
+  real* rhs_aff = malloc(sizeof(real) * (size_t)m);
+  if (!aux || !rhs_aff) {
+    free(aux);
+    free(rhs_aff);
+    state_free(&S);
+    return ORC_ERR_INVALID_ARG;
+  }
+  state_load(&S, A, b, c, x, y, s);
+  pc_info info;
+  st = pc_iterate_state(&S, (real)eta, aux, rhs_aff, &info);
+  if (out) {
+    out->gap = (double)info.gap;
+    out->mu = (double)info.mu;
+    out->mu_aff = (double)info.mu_aff;
+    out->sigma = (double)info.sigma;
+    out->alpha_aff_p = (double)info.a_aff_p;
+    out->alpha_aff_d = (double)info.a_aff_d;
+    out->alpha_p = (double)info.a_p;
+    out->alpha_d = (double)info.a_d;
+    out->min_pivot = (double)info.min_pivot;
+    out->fail_col = info.fail_col;
+    if (st != ORC_ERR_BREAKDOWN) {
+      store(out->dx_aff, aux, n);
+      store(out->dy_aff, aux + n, m);
+      store(out->ds_aff, aux + n + m, n);
+      store(out->dx, S.dx, n);
+      store(out->dy, S.dy, m);
+      store(out->ds, S.ds, n);
+      store(out->rhs_aff, rhs_aff, m);
+      store(out->rhs, S.rhs, m);
+    }
+  }
+  if (st == ORC_CONTINUE || st == ORC_ERR_LOST_INTERIOR) {
+    store(x, S.x, n);
+    store(y, S.y, m);
+    store(s, S.s, n);
+  }
+  free(aux);
+  free(rhs_aff);
+  state_free(&S);
+  return st;
+}
+
+/* The predictor-corrector loop: before each direction stop with
+ * ORC_CONVERGED when x^T s < gap_tol, or ORC_MAX_ITER after max_iter
+ * directions.  (x, y, s) in/out receive the last valid iterate; log
+ * (max_iter entries) may be NULL. */
+int orc_pc_solve(long m, long n, const double* A, const double* b, const double* c,
+                 double* x, double* y, double* s, double eta, double gap_tol, int max_iter,
+                 int* iters, orc_pc_log* log) {
+  int st = validate(m, n, A, b, c, x, y, s, eta);
+  if (iters) *iters = 0;
+  if (st != ORC_CONTINUE) return st;
+  if (max_iter < 0) return ORC_ERR_INVALID_ARG;
+  state S;
+  if (!state_alloc(&S, m, n)) return ORC_ERR_INVALID_ARG;
+  const long row = 2 * n + m;
+  real* aux = malloc(sizeof(real) * (size_t)(3 * n + m));
+  real* rhs_aff = malloc(sizeof(real) * (size_t)m);
+  real* keep = malloc(sizeof(real) * (size_t)row);
+  if (!aux || !rhs_aff || !keep) {
+    free(aux);
+    free(rhs_aff);
+    free(keep);
+    state_free(&S);
+    return ORC_ERR_INVALID_ARG;
+  }
+  state_load(&S, A, b, c, x, y, s);
+  int k = 0;
+  for (;;) {
+    real gap = dot(n, S.x, S.s);
+    if (gap < (real)gap_tol) { st = ORC_CONVERGED; break; }
+    if (k >= max_iter) { st = ORC_MAX_ITER; break; }
+    memcpy(keep, S.x, sizeof(real) * n);
+    memcpy(keep + n, S.y, sizeof(real) * m);
+    memcpy(keep + n + m, S.s, sizeof(real) * n);
+    pc_info info;
+    st = pc_iterate_state(&S, (real)eta, aux, rhs_aff, &info);
+    if (log) {
+      log[k].gap = (double)gap;
+      log[k].sigma = (double)info.sigma;
+      log[k].alpha_p = (double)info.a_p;
+      log[k].alpha_d = (double)info.a_d;
+      log[k].min_pivot = (double)info.min_pivot;
+    }
+    if (st == ORC_ERR_LOST_INTERIOR) {
+      memcpy(S.x, keep, sizeof(real) * n);
+      memcpy(S.y, keep + n, sizeof(real) * m);
+      memcpy(S.s, keep + n + m, sizeof(real) * n);
+    }
+    if (st == ORC_CONTINUE) { ++k; continue; }
+    break;
+  }
+  if (iters) *iters = k;
+  store(x, S.x, n);
+  store(y, S.y, m);
+  store(s, S.s, n);
+  free(aux);
+  free(rhs_aff);
+  free(keep);
+  state_free(&S);
+  return st;
 }

@@ -270,8 +270,117 @@ def check_jvp_vjp(prec="f64", m=6, n=20, seed=9, K=4, alpha=0.9):
     assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), abs(rhs)), (lhs, rhs)
 
 
+# ---------------------------------------------------------------- predictor-corrector
+def _pc_trajectory(m, n, seed, prec, eta=0.95, upto=60):
+    """Start iterate of every predictor-corrector step of one LP."""
+    lp = _lp(m, n, seed)
+    x, y, s = lp.x0.copy(), lp.y0.copy(), lp.s0.copy()
+    out = []
+    for _ in range(upto):
+        if x @ s < 1e-8:
+            break
+        r = oracle.pc_iterate(lp.A, lp.b, lp.c, x, y, s, eta, precision=prec)
+        out.append(((x, y, s), r))
+        if r.status != oracle.CONTINUE:
+            break
+        x, y, s = r.x, r.y, r.s
+    return lp, out
+
+
+def _kkt_solve(A, x, s, rp, rd, rc):
+    """The full Newton system (bigsystem) of the Section 3 algorithm,
+    unreduced: [A 0 0; 0 A^T I; S 0 X] [dx; dy; ds] = [rp; rd; rc], solved
+    densely by a library routine (test-only, independent of the oracle's
+    Section 5 reduction and Cholesky)."""
+    m, n = A.shape
+    K = np.zeros((m + 2 * n, 2 * n + m))
+    K[:m, :n] = A
+    K[m:m + n, n:n + m] = A.T
+    K[m:m + n, n + m:] = np.eye(n)
+    K[m + n:, :n] = np.diag(s)
+    K[m + n:, n + m:] = np.diag(x)
+    v = np.linalg.solve(K, np.concatenate([rp, rd, rc]))
+    return v[:n], v[n:n + m], v[n + m:]
+
+
+def check_pc_newton_systems(prec="f64", m=6, n=18, seed=12):
+    """Predictor-corrector (the Mehrotra method cited in the previous-work
+    section): both directions solve the unreduced Newton system, the
+    predictor with third right-hand side -Xs and the corrector with
+    -Xs - dx_aff o ds_aff + sigma mu e (sigma, mu and the predictor as the
+    oracle reports them).  Catches sign and dropped-term errors in the
+    reduction of either right-hand side."""
+    lp, traj = _pc_trajectory(m, n, seed, prec)
+    assert traj and traj[-1][1].status_name in ("CONTINUE",), traj[-1][1].status_name
+    for k, ((x, y, s), r) in enumerate(traj[:8]):
+        A = lp.A
+        rp, rd = lp.b - A @ x, lp.c - A.T @ y - s
+        dxa, dya, dsa = _kkt_solve(A, x, s, rp, rd, -x * s)
+        sc = lambda v: 1e-9 * max(1.0, np.max(np.abs(v)))
+        np.testing.assert_allclose(r.dx_aff, dxa, rtol=0, atol=sc(dxa), err_msg=f"dx_aff {k}")
+        np.testing.assert_allclose(r.dy_aff, dya, rtol=0, atol=sc(dya), err_msg=f"dy_aff {k}")
+        np.testing.assert_allclose(r.ds_aff, dsa, rtol=0, atol=sc(dsa), err_msg=f"ds_aff {k}")
+        rc = -x * s - r.dx_aff * r.ds_aff + r.sigma * r.mu
+        dx, dy, ds = _kkt_solve(A, x, s, rp, rd, rc)
+        np.testing.assert_allclose(r.dx, dx, rtol=0, atol=sc(dx), err_msg=f"dx {k}")
+        np.testing.assert_allclose(r.dy, dy, rtol=0, atol=sc(dy), err_msg=f"dy {k}")
+        np.testing.assert_allclose(r.ds, ds, rtol=0, atol=sc(ds), err_msg=f"ds {k}")
+
+
+def check_pc_steps(prec="f64", m=8, n=30, seed=13, eta=0.95):
+    """Predictor-corrector step lengths: each is the largest step keeping the
+    iterate non-negative (capped at 1; the corrector's scaled by eta), so the
+    predictor step reaches the boundary exactly when below 1, the corrector
+    step stops a fraction 1 - eta short of it; the iterate moves by
+    alpha_p (dx) and alpha_d (dy, ds); mu is the mean complementarity."""
+    lp, traj = _pc_trajectory(m, n, seed, prec, eta)
+    assert len(traj) >= 5
+    for k, ((x, y, s), r) in enumerate(traj):
+        if r.status != oracle.CONTINUE:
+            break
+        assert abs(r.mu - (x @ s) / n) <= 1e-14 * r.mu
+        for v, dv, a, cap in ((x, r.dx_aff, r.alpha_aff_p, 1.0), (s, r.ds_aff, r.alpha_aff_d, 1.0)):
+            w = v + a * dv
+            assert 0 < a <= cap and np.all(w >= -1e-14 * np.max(v)), (k, a)
+            if a < cap:
+                assert np.min(w / v) <= 1e-12, (k, a, np.min(w / v))
+        for v, dv, a in ((x, r.dx, r.alpha_p), (s, r.ds, r.alpha_d)):
+            assert 0 < a <= 1
+            if a < 1:
+                # a / eta reaches the boundary
+                w = v + (a / eta) * dv
+                assert abs(np.min(w / v)) <= 1e-12, (k, a, np.min(w / v))
+        np.testing.assert_allclose(r.x, x + r.alpha_p * r.dx, rtol=1e-15, atol=0)
+        np.testing.assert_allclose(r.y, y + r.alpha_d * r.dy, rtol=1e-15,
+                                   atol=1e-15 * np.max(np.abs(y)))
+        np.testing.assert_allclose(r.s, s + r.alpha_d * r.ds, rtol=1e-15, atol=0)
+        assert np.all(r.x > 0) and np.all(r.s > 0)
+        assert 0 <= r.sigma <= 1.0 + 1e-12, (k, r.sigma)
+
+
+def check_pc_optimum(prec="f64", seeds=(0, 1, 2), m=3, n=8):
+    """The predictor-corrector loop ends at the LP optimum that vertex
+    enumeration gives (Section 2), and at m=64, n=256 at the Section 3
+    algorithm's dual objective, in fewer iterations."""
+    for seed in seeds:
+        lp = _lp(m, n, seed)
+        z = _vertex_optimum(lp.A, lp.b, lp.c)
+        r = oracle.pc_solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95, 1e-10, 100,
+                            precision=prec)
+        assert r.status_name == "CONVERGED", (seed, r.status_name)
+        assert abs(lp.b @ r.y - z) <= 1e-8 * max(1, abs(z)), (seed, lp.b @ r.y, z)
+    lp = _lp(64, 256, 0)
+    r = oracle.pc_solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95, 1e-8, 100, precision=prec)
+    a = oracle.solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95, 1e-8, 200, precision=prec)
+    assert r.status_name == a.status_name == "CONVERGED"
+    assert abs(lp.b @ r.y - lp.b @ a.y) <= 1e-9 * abs(lp.b @ a.y)
+    assert r.iters < a.iters, (r.iters, a.iters)
+    assert np.linalg.norm(lp.A @ r.x - lp.b) <= 1e-9 * np.linalg.norm(lp.b)
+
+
 ALL_CHECKS = [
     check_psi1_example, check_newton_rows, check_gap_identity, check_m1_closed_form,
     check_normal_matrix_and_cholesky, check_cholesky_breakdown, check_egidi_maponi,
     check_vertex_enumeration, check_invariants_final, check_adjoint_fd, check_jvp_vjp,
+    check_pc_newton_systems, check_pc_steps, check_pc_optimum,
 ]

@@ -33,6 +33,16 @@ MUTANTS = {
     "jvp_sign": ("for (long j = 0; j < n; ++j) Tds[j] = Trd[j] - Tg[j];",
                  "for (long j = 0; j < n; ++j) Tds[j] = Trd[j] + Tg[j];"),
     "psi1_rule": ("real aeff = (psi == 1) ? (real)1 : alpha;", "real aeff = alpha;"),
+    "pc_corrector_term": ("rc[j] = -S->x[j] * S->s[j] - dxa[j] * dsa[j] + info->sigma * info->mu;",
+                          "rc[j] = -S->x[j] * S->s[j] + info->sigma * info->mu;"),
+    "pc_rhs_sign": ("t[j] = S->d[j] * S->rd[j] - S->x[j] - rc[j] / S->s[j];",
+                    "t[j] = S->d[j] * S->rd[j] - S->x[j] + rc[j] / S->s[j];"),
+    "pc_dual_step_on_x": ("S->x[j] = S->x[j] + info->a_p * S->dx[j];",
+                          "S->x[j] = S->x[j] + info->a_d * S->dx[j];"),
+    "pc_no_centring": ("rc[j] = -S->x[j] * S->s[j] - dxa[j] * dsa[j] + info->sigma * info->mu;",
+                       "rc[j] = -S->x[j] * S->s[j] - dxa[j] * dsa[j];"),
+    "pc_eta_dropped": ("info->a_p = eta * mp < 1 ? eta * mp : (real)1;",
+                       "info->a_p = mp < 1 ? mp : (real)1;"),
 }
 
 
