@@ -17,7 +17,8 @@ reverse-mode workload (64 LPs, K = 30 steps with a tape plus the reverse
 sweep, with the oracle's forward and reverse sweep on a sample beside it) and
 the mixed-precision comparison (m=8192, n=32768: one mixed solve against one
 FP64 solve, with the FP64 Cholesky and the FP32 and FP64 normal-matrix
-kernels against their peaks).
+kernels against their peaks), and the predictor-corrector variant (Mehrotra's
+method, cited in the paper's previous work) on the main instance.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants]
   python bench.py --mixed-compare   # m=8192, n=32768: mixed precision vs FP64, one solve each
@@ -293,6 +294,35 @@ def mixed_variant(lpgen, solver, capi, torch) -> dict:
     return out
 
 
+def pc_variant(lpgen, solver, capi, torch, T, m, n, affine_solves_per_s, steps=5) -> dict:
+    """The same instance as the main line, solved by the predictor-corrector
+    variant (one factorization and two solves per iteration) to the same gap:
+    LP solves/s beside the Section 3 algorithm's."""
+    handles = [solver.LP(*T, alpha=0.95, method="pc", profile=True) for _ in range(steps + 1)]
+    handles[0].solve(1e-8, 100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [h.solve(1e-8, 100) for h in handles[1:]]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tims = [h.timings() for h in handles[1:]]
+    tot = {k: sum(t[k] for t in tims) for k in tims[0]}
+    out = {
+        "workload": f"single LP m={m} n={n} (the main line's instance), Mehrotra "
+                    "predictor-corrector, eta 0.95, to gap 1e-8, FP64",
+        "lp_solves_per_s": steps / wall,
+        "ms_per_solve": wall * 1e3 / steps,
+        "iterations_per_solve": res[0]["iters"],
+        "statuses": sorted({capi.status_string(r["status"]) for r in res}),
+        "ms_per_iteration": tot["iter_ms"] / max(tot["iterations"], 1),
+        "dual_obj": res[0]["dual_obj"],
+        "speedup_vs_affine_scaling": (steps / wall) / affine_solves_per_s,
+    }
+    for h in handles:
+        h.close()
+    return out
+
+
 def mixed_compare():
     """m=8192, n=32768: one mixed-precision solve and one FP64 solve from the
     same start, with the per-iteration precision and refinement counts."""
@@ -478,6 +508,8 @@ def main():
         "avg_ms": tot["potrf_ms"] / tot["iterations"]}]
     if not args.no_variants:
         out["variants"] = {
+            "predictor_corrector": pc_variant(lpgen, solver, capi, torch, T, m, n,
+                                              out["value"]),
             "batched": batch_variant(lpgen, solver, capi, torch),
             "adjoint": adjoint_variant(lpgen, solver, capi, torch, not args.no_cpu_baseline),
             "mixed": mixed_variant(lpgen, solver, capi, torch),

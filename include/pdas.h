@@ -68,6 +68,18 @@ typedef enum lp_precision {
                         switching to FP64 for good (see lp_options)            */
 } lp_precision;
 
+typedef enum lp_method {
+  LP_METHOD_AFFINE = 0, /* the Section 3 algorithm (primal-dual affine scaling) */
+  LP_METHOD_PC = 1      /* Mehrotra's predictor-corrector, which Section 4
+                           (previous work) cites: the Section 3 direction as
+                           predictor, sigma = (mu_aff/mu)^3 from its steps to
+                           the boundary, a corrector solve with the same factor
+                           and third right-hand side -Xs - dX_aff dS_aff e +
+                           sigma mu e, then primal and dual steps of
+                           min(1, alpha * step to the boundary).  FP64 only, no
+                           tape (LP_ERR_INVALID_ARG otherwise); not for batches */
+} lp_method;
+
 typedef struct lp_options {
   double alpha;            /* step fraction, 0 < alpha < 1 (Section 3)          */
   int32_t precision;       /* lp_precision                                       */
@@ -95,7 +107,7 @@ typedef struct lp_options {
                               choice) or 1..64; non-zero selects split-K (with
                               128 tiles unless syrk_tile says 64)                */
   int32_t syrk32_splits;   /* FP32 normal-matrix split (MIXED): 0 or 1..64      */
-  int32_t reserved;        /* must be 0                                          */
+  int32_t method;          /* lp_method (default LP_METHOD_AFFINE)               */
 } lp_options;
 
 /* Fill *opt with the defaults: alpha 0.95, FP64, no tape, switch gap 1e-6,
@@ -107,13 +119,16 @@ typedef struct lp_iter_info {
   int32_t status;         /* lp_status of the step (LP_OK while continuing)    */
   double gap_before;      /* x^T s before the step                             */
   double gap_after;       /* x^T s after the step                              */
-  double psi;             /* ratio-test value                                  */
+  double psi;             /* ratio-test value (NaN for LP_METHOD_PC)           */
   double t;               /* step length alpha_eff / psi                       */
   int64_t argmax;         /* j in [0,n): x-block; n + j: s-block                */
   double min_pivot;       /* smallest Cholesky pivot (squared diagonal of L)    */
   int32_t precision_used; /* lp_precision of this step's factor                */
   int32_t refine_steps;   /* refinement steps taken (MIXED)                    */
   double refine_resid;    /* estimated relative error of dy after refinement   */
+  double alpha_primal;    /* step applied to x (LP_METHOD_AFFINE: t)           */
+  double alpha_dual;      /* step applied to y and s (LP_METHOD_AFFINE: t)     */
+  double sigma;           /* centring parameter (LP_METHOD_PC; 0 otherwise)    */
 } lp_iter_info;
 
 typedef struct lp_result {

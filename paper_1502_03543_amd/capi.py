@@ -33,6 +33,10 @@ LP_ERR_DEVICE = -9
 LP_PREC_FP64 = 0
 LP_PREC_MIXED = 1
 
+# lp_method
+LP_METHOD_AFFINE = 0
+LP_METHOD_PC = 1
+
 
 class lp_options(C.Structure):
     _fields_ = [
@@ -46,7 +50,7 @@ class lp_options(C.Structure):
         ("syrk_tile", C.c_int32),
         ("syrk_splits", C.c_int32),
         ("syrk32_splits", C.c_int32),
-        ("reserved", C.c_int32),
+        ("method", C.c_int32),
     ]
 
 
@@ -63,6 +67,9 @@ class lp_iter_info(C.Structure):
         ("precision_used", C.c_int32),
         ("refine_steps", C.c_int32),
         ("refine_resid", C.c_double),
+        ("alpha_primal", C.c_double),
+        ("alpha_dual", C.c_double),
+        ("sigma", C.c_double),
     ]
 
     def as_dict(self) -> dict:

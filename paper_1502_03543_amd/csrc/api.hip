@@ -95,6 +95,12 @@ struct lp_handle {
   int last_prec = LP_PREC_FP64;
   int last_refine = 0;
   double last_resid = 0.0;
+  // predictor-corrector (lp_options.method == LP_METHOD_PC)
+  bool pc = false;
+  double *dxa = nullptr, *dsa = nullptr;  // predictor direction
+  double* pcq = nullptr;                  // (dx_aff o ds_aff - sigma mu) / s
+  double* amin = nullptr;                 // per-block steps to the boundary
+  double* mupart = nullptr;               // per-block partials of mu_aff
   // phase timing (lp_options.profile)
   enum { EV_ITER0, EV_SYRK0, EV_SYRKK0, EV_SYRKK1, EV_SYRK1, EV_CHOL1, EV_TRSV1, EV_ITER1, EV_N };
   hipEvent_t ev[EV_N] = {};
@@ -166,6 +172,13 @@ void carve(lp_handle* h, Carver& cv) {
     h->vtmp = cv.take<double>(n);
     h->rnorms = cv.take<double>(4);
   }
+  if (h->opt.method == LP_METHOD_PC) {
+    h->dxa = cv.take<double>(n);
+    h->dsa = cv.take<double>(n);
+    h->pcq = cv.take<double>(n);
+    h->amin = cv.take<double>(2 * (size_t)h->ndir);
+    h->mupart = cv.take<double>(h->ndir);
+  }
   h->tape_cap = h->opt.tape_capacity > 0 ? h->opt.tape_capacity : 0;
   h->tape = h->tape_cap ? cv.take<double>((size_t)(h->tape_cap + 1) * (3 * n + m)) : nullptr;
   if (h->tape_cap) {
@@ -200,7 +213,11 @@ bool valid_opts(const lp_options* o) {
   if (o->tape_capacity < 0) return false;
   if (o->syrk_tile != 0 && o->syrk_tile != 64 && o->syrk_tile != 128) return false;
   if (o->syrk_splits < 0 || o->syrk_splits > 64 || o->syrk32_splits < 0 ||
-      o->syrk32_splits > 64 || o->reserved != 0)
+      o->syrk32_splits > 64)
+    return false;
+  if (o->method != LP_METHOD_AFFINE && o->method != LP_METHOD_PC) return false;
+  // the predictor-corrector runs in FP64 and has no reverse mode
+  if (o->method == LP_METHOD_PC && (o->precision != LP_PREC_FP64 || o->tape_capacity != 0))
     return false;
   return true;
 }
@@ -306,6 +323,7 @@ lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const
   launch_copy(s, h->s[0], s0, n);
   h->cur = 0;
   launch_fill_i32(s, h->trsv_sync, 0, 4 + 2 * h->nblk);
+  h->pc = h->opt.method == LP_METHOD_PC;
   if (h->opt.precision == LP_PREC_MIXED) {
     h->mixed = true;
     h->fp32_mode = true;
@@ -455,8 +473,47 @@ static bool solve_mixed(lp_handle* h, bool* ok) {
   return true;
 }
 
+// One predictor-corrector iteration (LP_METHOD_PC): the Section 3 direction
+// as predictor (normal matrix, factor, the right-hand side carried through
+// the factorization), its steps to the boundary and the centring parameter,
+// then the corrector solve with the same factor, the corrector direction and
+// the step, from the current iterate into the other buffer.
+static void enqueue_pc_iteration(lp_handle* h) {
+  const long m = h->m, n = h->n;
+  hipStream_t s = h->st;
+  const int cur = h->cur, nxt = cur ^ 1;
+  mark(h, lp_handle::EV_ITER0);
+  launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
+  launch_prep(s, n, h->x[cur], h->s[cur], h->rd[cur], h->d, h->w);
+  launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
+  mark(h, lp_handle::EV_SYRK0);
+  solve_fp64(h);  // dy: the predictor
+  launch_gemv_t(s, m, n, h->A, h->dy, h->y[cur], h->P1, h->P2);
+  launch_pc_aff(s, n, h->P1, h->P2, h->nchunks, h->rd[cur], h->x[cur], h->s[cur], h->d, h->dxa,
+                h->dsa, h->gy, h->amin);
+  launch_pc_corr(s, n, h->gap, h->amin, h->x[cur], h->s[cur], h->rd[cur], h->d, h->dxa, h->dsa,
+                 h->mupart, h->pcq, h->w, h->info);
+  launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
+  launch_fill_i32(s, h->trsv_sync, 0, 4 + 2 * h->nblk);
+  launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
+  launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
+  mark(h, lp_handle::EV_TRSV1);
+  launch_gemv_t(s, m, n, h->A, h->dy, nullptr, h->P1, nullptr);
+  launch_pc_dir(s, n, h->P1, h->nchunks, h->rd[cur], h->x[cur], h->s[cur], h->d, h->pcq, h->dx,
+                h->ds, h->g, h->amin, h->zpart, h->npart);
+  launch_pc_step(s, m, n, h->opt.alpha, h->amin, h->zpart, h->npart, h->dy, h->x[cur], h->y[cur],
+                 h->s[cur], h->dx, h->ds, h->g, h->gy, h->c, h->x[nxt], h->y[nxt], h->s[nxt],
+                 h->rd[nxt], h->gap_part, h->lost_part, h->info);
+  launch_finish(s, h->nstep, h->gap_part, h->lost_part, h->info);
+  mark(h, lp_handle::EV_ITER1);
+}
+
 // Enqueue one iteration from the current iterate into the other buffer.
 static bool enqueue_iteration(lp_handle* h) {
+  if (h->pc) {
+    enqueue_pc_iteration(h);
+    return true;
+  }
   const long m = h->m, n = h->n;
   hipStream_t s = h->st;
   const int cur = h->cur, nxt = cur ^ 1;
@@ -536,6 +593,9 @@ lp_status lp_iterate(lp_handle* h, lp_iter_info* info) {
     info->precision_used = h->last_prec;
     info->refine_steps = h->last_prec == LP_PREC_MIXED ? h->last_refine : 0;
     info->refine_resid = h->last_prec == LP_PREC_MIXED ? h->last_resid : 0.0;
+    info->alpha_primal = h->pc ? di.alpha_p : di.t;
+    info->alpha_dual = h->pc ? di.alpha_d : di.t;
+    info->sigma = h->pc ? di.sigma : 0.0;
   }
   if (stepped) {
     h->cur ^= 1;

@@ -245,7 +245,7 @@ lp_status lp_batch_workspace_size(int32_t count, const int64_t* m, const int64_t
   lp_options_default(&o);
   if (opt) o = *opt;
   if (!(o.alpha > 0.0 && o.alpha < 1.0) || o.tape_capacity < 0) return LP_ERR_INVALID_ARG;
-  if (o.precision != LP_PREC_FP64) return LP_ERR_INVALID_ARG;
+  if (o.precision != LP_PREC_FP64 || o.method != LP_METHOD_AFFINE) return LP_ERR_INVALID_ARG;
   lp_batch h;
   h.count = count;
   h.opt = o;

@@ -451,7 +451,289 @@ __global__ void k_lower_f32_to_f64(long m, const float* __restrict__ L32, long l
     L64[i * ld64 + j] = (double)L32[i * ld32 + j];
 }
 
+// ---- predictor-corrector (Mehrotra) ---------------------------------------
+// The method the previous-work section cites: the affine-scaling (Section 3)
+// direction as predictor, a centring parameter from its step, and a second
+// solve with the same factor whose third right-hand side carries the
+// second-order term dX_aff dS_aff e and the centring target sigma mu e;
+// primal and dual steps are eta times the step to the boundary, capped at 1.
+
+// Block minimum; result valid in thread 0.
+__device__ double block_min(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = INFINITY;
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) r = fmin(r, sh[i]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// Steps to the boundary from the per-block minima (every block reduces the
+// same partials, so every block holds the same value): thread 0's result.
+__device__ void reduce_steps(int nparts, const double* amin, double* s_ap, double* s_ad) {
+  if (threadIdx.x == 0) {
+    double ap = INFINITY, ad = INFINITY;
+    for (int k = 0; k < nparts; ++k) {
+      ap = fmin(ap, amin[2 * k]);
+      ad = fmin(ad, amin[2 * k + 1]);
+    }
+    *s_ap = ap;
+    *s_ad = ad;
+  }
+  __syncthreads();
+}
+
+// Predictor: g = A^T dy_aff, g_y = A^T y (chunk partials, in chunk order),
+// ds_aff = r_d - g, dx_aff = -x - d o ds_aff, and per block the steps to
+// the boundary min over dx_j < 0 of -x_j/dx_j (and for s, ds).
+__global__ __launch_bounds__(256) void k_pc_aff(long n, const double* P1, const double* P2,
+                                                int nchunks, const double* rd, const double* x,
+                                                const double* s, const double* d, double* dxa,
+                                                double* dsa, double* gy, double* amin) {
+  __shared__ double sh[4];
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double rp = INFINITY, rq = INFINITY;
+  if (j < n) {
+    double g = 0, gyv = 0;
+#pragma unroll 8
+    for (int k = 0; k < nchunks; ++k) g += P1[(long)k * n + j];
+#pragma unroll 8
+    for (int k = 0; k < nchunks; ++k) gyv += P2[(long)k * n + j];
+    gy[j] = gyv;
+    const double dsj = rd[j] - g;
+    const double dxj = -x[j] - d[j] * dsj;
+    dsa[j] = dsj;
+    dxa[j] = dxj;
+    if (dxj < 0) rp = -x[j] / dxj;
+    if (dsj < 0) rq = -s[j] / dsj;
+  }
+  const double bp = block_min(rp, sh);
+  const double bq = block_min(rq, sh);
+  if (threadIdx.x == 0) {
+    amin[2 * blockIdx.x] = bp;
+    amin[2 * blockIdx.x + 1] = bq;
+  }
+}
+
+// mu_aff partials: per block, sum of (x + a_p dx_aff)(s + a_d ds_aff) with
+// the predictor steps a = min(1, step to the boundary).
+__global__ __launch_bounds__(256) void k_pc_mu(long n, int nparts, const double* amin,
+                                               const double* x, const double* s,
+                                               const double* dxa, const double* dsa,
+                                               double* mupart) {
+  __shared__ double sh[4];
+  __shared__ double s_ap, s_ad;
+  reduce_steps(nparts, amin, &s_ap, &s_ad);
+  const double ap = fmin(1.0, s_ap), ad = fmin(1.0, s_ad);
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const double v = (j < n) ? (x[j] + ap * dxa[j]) * (s[j] + ad * dsa[j]) : 0.0;
+  const double bs = block_sum(v, sh);
+  if (threadIdx.x == 0) mupart[blockIdx.x] = bs;
+}
+
+// Centring sigma = (mu_aff / mu)^3 with mu = gap / n; the corrector's
+// column term q = (dx_aff o ds_aff - sigma mu) / s and w = d o r_d + q, so
+// that the corrector's reduced right-hand side is b + A w and its
+// dx = -x - q - d o ds.
+__global__ __launch_bounds__(256) void k_pc_corr(long n, int nparts, const double* mupart,
+                                                 const double* amin, double gap,
+                                                 const double* rd, const double* s,
+                                                 const double* d, const double* dxa,
+                                                 const double* dsa, double* q, double* w,
+                                                 DevInfo* info) {
+  __shared__ double s_sig;
+  if (threadIdx.x == 0) {
+    double acc = 0;
+    for (int k = 0; k < nparts; ++k) acc += mupart[k];
+    const double mu = gap / (double)n, r = (acc / (double)n) / mu;
+    s_sig = r * r * r;
+    if (blockIdx.x == 0) {
+      double ap = INFINITY, ad = INFINITY;
+      for (int k = 0; k < nparts; ++k) {
+        ap = fmin(ap, amin[2 * k]);
+        ad = fmin(ad, amin[2 * k + 1]);
+      }
+      info->sigma = s_sig;
+      info->mu_aff = acc / (double)n;
+      info->alpha_aff_p = fmin(1.0, ap);
+      info->alpha_aff_d = fmin(1.0, ad);
+    }
+  }
+  __syncthreads();
+  const double smu = s_sig * (gap / (double)n);
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double qj = (dxa[j] * dsa[j] - smu) / s[j];
+  q[j] = qj;
+  w[j] = d[j] * rd[j] + qj;
+}
+
+// Corrector direction: g = A^T dy, ds = r_d - g, dx = -x - q - d o ds, the
+// per-block steps to the boundary and the zero / non-finite flags.
+__global__ __launch_bounds__(256) void k_pc_dir(long n, const double* P1, int nchunks,
+                                                const double* rd, const double* x,
+                                                const double* s, const double* d,
+                                                const double* q, double* dx, double* ds,
+                                                double* gout, double* amin, int* zpart,
+                                                int* npart) {
+  __shared__ double sh[4];
+  __shared__ int shz, shn;
+  if (threadIdx.x == 0) {
+    shz = 0;
+    shn = 0;
+  }
+  __syncthreads();
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double rp = INFINITY, rq = INFINITY;
+  int nz = 0, nf = 0;
+  if (j < n) {
+    double g = 0;
+#pragma unroll 8
+    for (int k = 0; k < nchunks; ++k) g += P1[(long)k * n + j];
+    gout[j] = g;
+    const double dsj = rd[j] - g;
+    const double dxj = -x[j] - q[j] - d[j] * dsj;
+    ds[j] = dsj;
+    dx[j] = dxj;
+    if (dxj < 0) rp = -x[j] / dxj;
+    if (dsj < 0) rq = -s[j] / dsj;
+    nz = (dxj != 0.0) | (dsj != 0.0);
+    nf = !isfinite(dxj) | !isfinite(dsj);
+  }
+  if (nz) atomicOr(&shz, 1);
+  if (nf) atomicOr(&shn, 1);
+  const double bp = block_min(rp, sh);
+  const double bq = block_min(rq, sh);
+  if (threadIdx.x == 0) {
+    amin[2 * blockIdx.x] = bp;
+    amin[2 * blockIdx.x + 1] = bq;
+    zpart[blockIdx.x] = shz;
+    npart[blockIdx.x] = shn;
+  }
+}
+
+// Corrector step: a_p = min(1, eta a_max_p), a_d = min(1, eta a_max_d);
+// x += a_p dx, y += a_d dy, s += a_d ds; next r_d = c - (A^T y + a_d A^T dy)
+// - s; gap partials; statuses as for the Section 3 step (no psi == 1 rule).
+__global__ __launch_bounds__(256) void k_pc_step(long m, long n, double eta, int nparts,
+                                                 const double* amin, const int* zpart,
+                                                 const int* npart, const double* dy,
+                                                 const double* x, const double* y,
+                                                 const double* s, const double* dx,
+                                                 const double* ds, const double* g,
+                                                 const double* gy, const double* c, double* xn,
+                                                 double* yn, double* sn, double* rdn,
+                                                 double* gap_part, int* lost_part,
+                                                 DevInfo* info) {
+  __shared__ double s_ap, s_ad;
+  __shared__ int s_zero, s_nf, s_dyz, s_lost;
+  __shared__ double sh[4];
+  if (threadIdx.x == 0) {
+    double ap = INFINITY, ad = INFINITY;
+    int z = 0, nf = 0;
+    for (int k = 0; k < nparts; ++k) {
+      ap = fmin(ap, amin[2 * k]);
+      ad = fmin(ad, amin[2 * k + 1]);
+      z |= zpart[k];
+      nf |= npart[k];
+    }
+    s_ap = fmin(1.0, eta * ap);
+    s_ad = fmin(1.0, eta * ad);
+    s_zero = !z;
+    s_nf = nf;
+    s_dyz = 0;
+    s_lost = 0;
+  }
+  __syncthreads();
+  if (s_zero) {
+    int nzy = 0;
+    for (long i = threadIdx.x; i < m; i += blockDim.x) nzy |= (dy[i] != 0.0);
+    if (nzy) atomicOr(&s_dyz, 1);
+    __syncthreads();
+  }
+  const bool zero_dir = s_zero && !s_dyz;
+  const double ap = s_ap, ad = s_ad;
+  const bool broke = info->chol_fail != INT_MAX || info->trsv_err != 0;
+  const bool bad = s_nf || !(ap > 0) || !(ad > 0) || !isfinite(ap) || !isfinite(ad);
+  const bool update = !broke && !zero_dir && !bad;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double gp = 0;
+  int lost = 0;
+  if (update) {
+    if (i < n) {
+      const double xv = x[i] + ap * dx[i];
+      const double sv = s[i] + ad * ds[i];
+      xn[i] = xv;
+      sn[i] = sv;
+      rdn[i] = c[i] - (gy[i] + ad * g[i]) - sv;
+      gp = xv * sv;
+      lost = !(xv > 0) | !(sv > 0);
+    }
+    if (i < m) yn[i] = y[i] + ad * dy[i];
+  }
+  if (lost) atomicOr(&s_lost, 1);
+  const double bs = block_sum(gp, sh);
+  if (threadIdx.x == 0) {
+    gap_part[blockIdx.x] = bs;
+    lost_part[blockIdx.x] = s_lost;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    info->psi = NAN;  // no ratio-test value in this method
+    info->argmax = -1;
+    info->alpha_p = update ? ap : 0.0;
+    info->alpha_d = update ? ad : 0.0;
+    info->t = info->alpha_p;
+    info->zero_dir = zero_dir;
+    info->nonfinite = s_nf;
+    int st = LP_OK;
+    if (info->trsv_err) st = LP_ERR_DEVICE;
+    else if (info->chol_fail != INT_MAX) st = LP_ERR_BREAKDOWN;
+    else if (zero_dir) st = LP_OPTIMAL_ZERO_DIR;
+    else if (bad) st = LP_ERR_NONPOS_PSI;
+    info->status = st;
+  }
+}
+
 }  // namespace
+
+void launch_pc_aff(hipStream_t st, long n, const double* P1, const double* P2, int nchunks,
+                   const double* rd, const double* x, const double* s, const double* d,
+                   double* dxa, double* dsa, double* gy, double* amin) {
+  hipLaunchKernelGGL(k_pc_aff, dim3(dir_blocks(n)), dim3(256), 0, st, n, P1, P2, nchunks, rd, x,
+                     s, d, dxa, dsa, gy, amin);
+}
+
+void launch_pc_corr(hipStream_t st, long n, double gap, const double* amin, const double* x,
+                    const double* s, const double* rd, const double* d, const double* dxa,
+                    const double* dsa, double* mupart, double* q, double* w, DevInfo* info) {
+  const int nb = dir_blocks(n);
+  hipLaunchKernelGGL(k_pc_mu, dim3(nb), dim3(256), 0, st, n, nb, amin, x, s, dxa, dsa, mupart);
+  hipLaunchKernelGGL(k_pc_corr, dim3(nb), dim3(256), 0, st, n, nb, mupart, amin, gap, rd, s, d,
+                     dxa, dsa, q, w, info);
+}
+
+void launch_pc_dir(hipStream_t st, long n, const double* P1, int nchunks, const double* rd,
+                   const double* x, const double* s, const double* d, const double* q,
+                   double* dx, double* ds, double* g, double* amin, int* zpart, int* npart) {
+  hipLaunchKernelGGL(k_pc_dir, dim3(dir_blocks(n)), dim3(256), 0, st, n, P1, nchunks, rd, x, s,
+                     d, q, dx, ds, g, amin, zpart, npart);
+}
+
+void launch_pc_step(hipStream_t st, long m, long n, double eta, const double* amin,
+                    const int* zpart, const int* npart, const double* dy, const double* x,
+                    const double* y, const double* s, const double* dx, const double* ds,
+                    const double* g, const double* gy, const double* c, double* xn, double* yn,
+                    double* sn, double* rdn, double* gap_part, int* lost_part, DevInfo* info) {
+  hipLaunchKernelGGL(k_pc_step, dim3(step_blocks(m, n)), dim3(256), 0, st, m, n, eta,
+                     dir_blocks(n), amin, zpart, npart, dy, x, y, s, dx, ds, g, gy, c, xn, yn,
+                     sn, rdn, gap_part, lost_part, info);
+}
 
 void launch_check_inputs(hipStream_t st, long m, long n, const double* A, const double* b,
                          const double* c, const double* x, const double* y, const double* s,

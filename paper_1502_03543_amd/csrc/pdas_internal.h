@@ -25,6 +25,8 @@ struct DevInfo {
   int lost;              // some updated x_j or s_j <= 0
   int nonfinite;         // psi or a direction component is not finite
   int pad[2];
+  // predictor-corrector steps (LP_METHOD_PC)
+  double sigma, mu_aff, alpha_aff_p, alpha_aff_d, alpha_p, alpha_d;
 };
 
 // Device-side scalar results of input validation.
@@ -74,6 +76,22 @@ void launch_finish(hipStream_t st, int nparts, const double* gap_part, const int
 void launch_gap(hipStream_t st, long n, const double* x, const double* s, double* gap_part,
                 double* out);
 void launch_copy(hipStream_t st, double* dst, const double* src, long count);
+// predictor-corrector (LP_METHOD_PC); amin: 2 * dir_blocks(n) doubles of
+// per-block steps to the boundary, mupart: dir_blocks(n) doubles
+void launch_pc_aff(hipStream_t st, long n, const double* P1, const double* P2, int nchunks,
+                   const double* rd, const double* x, const double* s, const double* d,
+                   double* dxa, double* dsa, double* gy, double* amin);
+void launch_pc_corr(hipStream_t st, long n, double gap, const double* amin, const double* x,
+                    const double* s, const double* rd, const double* d, const double* dxa,
+                    const double* dsa, double* mupart, double* q, double* w, DevInfo* info);
+void launch_pc_dir(hipStream_t st, long n, const double* P1, int nchunks, const double* rd,
+                   const double* x, const double* s, const double* d, const double* q,
+                   double* dx, double* ds, double* g, double* amin, int* zpart, int* npart);
+void launch_pc_step(hipStream_t st, long m, long n, double eta, const double* amin,
+                    const int* zpart, const int* npart, const double* dy, const double* x,
+                    const double* y, const double* s, const double* dx, const double* ds,
+                    const double* g, const double* gy, const double* c, double* xn, double* yn,
+                    double* sn, double* rdn, double* gap_part, int* lost_part, DevInfo* info);
 // mixed precision helpers
 void launch_to_f32(hipStream_t st, long count, const double* src, float* dst);
 void launch_colsq(hipStream_t st, long m, long n, const double* A, double* out);

@@ -17,13 +17,15 @@ runs take minutes, so that the GPU tests can compare against them directly:
   batch512_seed0.json          512 LPs, seeds 0..511, shapes m ~ U{16..256},
                                n = round(r m), r ~ U(3, 5), alpha 0.95, gap
                                1e-8: per-LP status, K and objectives
+  lp2048x8192_seed0_pc.json    the m=2048 instance under the predictor-corrector
+                               variant: status, K, objectives, per-iteration log
   fd_lp256x1024_K30.json       64-LP reverse-mode workload (m=256, n=1024,
                                K=30, alpha 0.9, loss w^T x_K): central
                                differences of the loss along seeded directions
                                of A, b and c, in the long-double oracle, at
                                h = 1e-6 and h/2, for a sample of LPs
 
-Usage: python tests/golden/make_golden.py [c1] [c2] [c3] [c4] [c5]
+Usage: python tests/golden/make_golden.py [c1] [c2] [c2pc] [c3] [c4] [c5]
 (no argument: all).  The m=2048 solve takes a few minutes on 8 cores, the
 m=8192 direction several more.
 """
@@ -107,6 +109,18 @@ def c2():
     _dump("lp2048x8192_seed0.json", rec)
 
 
+def c2pc():
+    """The same m=2048 instance solved by the predictor-corrector oracle."""
+    lp = lpgen.gen_lp(2048, 8192, 0)
+    t0 = time.time()
+    ro = oracle.pc_solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95, 1e-8, 100)
+    rec = dict(m=2048, n=8192, seed=0, eta=0.95, gap_tol=1e-8, status=ro.status_name,
+               iters=ro.iters, dual_obj=float(lp.b @ ro.y), primal_obj=float(lp.c @ ro.x),
+               gap=float(ro.x @ ro.s), log=ro.log, oracle_seconds=round(time.time() - t0, 2),
+               oracle_threads=oracle.num_threads())
+    _dump("lp2048x8192_seed0_pc.json", rec)
+
+
 def c3():
     t0 = time.time()
     lp = lpgen.gen_lp(8192, 32768, 0)
@@ -155,7 +169,7 @@ def c5():
 
 
 if __name__ == "__main__":
-    todo = sys.argv[1:] or ["c1", "c2", "c4", "c5", "c3"]
+    todo = sys.argv[1:] or ["c1", "c2", "c2pc", "c4", "c5", "c3"]
     for name in todo:
         t0 = time.time()
         globals()[name]()

@@ -51,3 +51,26 @@ def test_setup_rejects_bad_workspace_without_touching_device():
     st = capi.lp_setup(C.byref(h), 16, 8, dummy, dummy, dummy, dummy, dummy, dummy,
                        C.byref(o), dummy, 1 << 30, None)
     assert st == capi.LP_ERR_SHAPE
+
+
+def test_method_validation():
+    """LP_METHOD_PC runs in FP64 without a tape and not in batches; an unknown
+    method is rejected."""
+    o = capi.lp_options()
+    capi.lp_options_default(C.byref(o))
+    assert o.method == capi.LP_METHOD_AFFINE
+    sz = C.c_size_t(0)
+    o.method = capi.LP_METHOD_PC
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_OK
+    o.precision = capi.LP_PREC_MIXED
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+    o.precision = capi.LP_PREC_FP64
+    o.tape_capacity = 4
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+    o.tape_capacity = 0
+    o.method = 2
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+    o.method = capi.LP_METHOD_PC
+    m = (C.c_int64 * 2)(16, 20)
+    n = (C.c_int64 * 2)(40, 60)
+    assert capi.lp_batch_workspace_size(2, m, n, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
