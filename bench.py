@@ -17,8 +17,10 @@ reverse-mode workload (64 LPs, K = 30 steps with a tape plus the reverse
 sweep, with the oracle's forward and reverse sweep on a sample beside it) and
 the mixed-precision comparison (m=8192, n=32768: one mixed solve against one
 FP64 solve, with the FP64 Cholesky and the FP32 and FP64 normal-matrix
-kernels against their peaks), and the predictor-corrector variant (Mehrotra's
-method, cited in the paper's previous work) on the main instance.
+kernels against their peaks), the predictor-corrector variant (Mehrotra's
+method, cited in the paper's previous work) on the main instance, and the
+paper's own Woodbury / Egidi-Maponi direction solver at m=64, n=256 beside the
+Cholesky path.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants]
   python bench.py --mixed-compare   # m=8192, n=32768: mixed precision vs FP64, one solve each
@@ -323,6 +325,53 @@ def pc_variant(lpgen, solver, capi, torch, T, m, n, affine_solves_per_s, steps=5
     return out
 
 
+def woodbury_variant(lpgen, solver, capi, torch, steps=20) -> dict:
+    """m=64, n=256 (seed 0): the paper's Woodbury / Egidi-Maponi direction
+    solver against the normal-matrix + Cholesky path, whole solves to gap
+    1e-8 with inputs resident, and the recurrence kernel's rate (about
+    2 m n^2 flops per iteration, in one compute unit) against that compute
+    unit's FP64 vector peak."""
+    import numpy as np
+
+    m, n = 64, 256
+    lp = lpgen.gen_lp(m, n, 0)
+    dev = torch.device("cuda:0")
+    T = [torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+         for v in (lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0)]
+    out = {"workload": f"single LP m={m} n={n} (seed 0), alpha 0.95, to gap 1e-8, FP64"}
+    for name in ("woodbury", "cholesky"):
+        hs = [solver.LP(*T, alpha=0.95, solver=name, profile=True) for _ in range(steps + 1)]
+        hs[0].solve(1e-8, 200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [h.solve(1e-8, 200) for h in hs[1:]]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tims = [h.timings() for h in hs[1:]]
+        tot = {k: sum(t[k] for t in tims) for k in tims[0]}
+        it = max(tot["iterations"], 1)
+        out[name] = {"lp_solves_per_s": steps / wall, "iterations_per_solve": res[0]["iters"],
+                     "statuses": sorted({capi.status_string(r["status"]) for r in res}),
+                     "dual_obj": res[0]["dual_obj"], "ms_per_iteration": tot["iter_ms"] / it,
+                     "direction_solve_ms_per_iteration":
+                         (tot["normal_ms"] + tot["potrf_ms"] + tot["trsv_ms"]) / it}
+        if name == "woodbury":
+            flops = 2.0 * m * n * n
+            ms = tot["potrf_ms"] / it  # x0 solves plus the recurrence kernel
+            a = flops / (ms * 1e-3) / 1e9
+            peak_cu = PEAK_FP64_MFMA_TFLOPS * 1e3 / 256  # one CU's share, GFLOP/s
+            out[name]["recurrence_roofline"] = {
+                "kernel": "k_woodbury (n rank-one terms in one workgroup, Y in LDS)",
+                "bound": "lds/latency (one compute unit)", "achieved": a, "peak": peak_cu,
+                "unit": "GFLOP/s", "frac": a / peak_cu, "algorithmic_flops_per_launch": flops,
+                "avg_ms": ms}
+        for h in hs:
+            h.close()
+    out["woodbury_vs_cholesky"] = (out["woodbury"]["lp_solves_per_s"] /
+                                   out["cholesky"]["lp_solves_per_s"])
+    return out
+
+
 def mixed_compare():
     """m=8192, n=32768: one mixed-precision solve and one FP64 solve from the
     same start, with the per-iteration precision and refinement counts."""
@@ -510,6 +559,7 @@ def main():
         out["variants"] = {
             "predictor_corrector": pc_variant(lpgen, solver, capi, torch, T, m, n,
                                               out["value"]),
+            "woodbury": woodbury_variant(lpgen, solver, capi, torch),
             "batched": batch_variant(lpgen, solver, capi, torch),
             "adjoint": adjoint_variant(lpgen, solver, capi, torch, not args.no_cpu_baseline),
             "mixed": mixed_variant(lpgen, solver, capi, torch),

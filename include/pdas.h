@@ -80,6 +80,25 @@ typedef enum lp_method {
                            tape (LP_ERR_INVALID_ARG otherwise); not for batches */
 } lp_method;
 
+typedef enum lp_solver {
+  LP_SOLVER_CHOLESKY = 0, /* normal matrix on the matrix cores, blocked Cholesky,
+                             triangular solves (Section 5.1's usual method)     */
+  LP_SOLVER_WOODBURY = 1  /* the paper's Section 5 solver: A D A^T split as
+                             A A^T plus the rank-one terms (d_l - 1) a_l a_l^T,
+                             applied by the Egidi-Maponi recurrence to
+                             (A A^T)^-1 [A | rhs] (factor of A A^T and
+                             (A A^T)^-1 A formed once at lp_setup).  The n terms
+                             run in one workgroup with Y in LDS, so it needs
+                             8 ((n + 1) ld + 2 m) <= 160 KiB, ld = m rounded up
+                             to odd (LP_ERR_SHAPE otherwise: e.g. m = 64,
+                             n = 256 fits); FP64, LP_METHOD_AFFINE, no tape
+                             (LP_ERR_INVALID_ARG otherwise).  A rank-deficient
+                             A makes lp_setup return LP_ERR_BREAKDOWN; a
+                             recurrence denominator that is not a finite
+                             positive number ends the run with it, and
+                             min_pivot reports the smallest denominator      */
+} lp_solver;
+
 typedef struct lp_options {
   double alpha;            /* step fraction, 0 < alpha < 1 (Section 3)          */
   int32_t precision;       /* lp_precision                                       */
@@ -108,6 +127,8 @@ typedef struct lp_options {
                               128 tiles unless syrk_tile says 64)                */
   int32_t syrk32_splits;   /* FP32 normal-matrix split (MIXED): 0 or 1..64      */
   int32_t method;          /* lp_method (default LP_METHOD_AFFINE)               */
+  int32_t solver;          /* lp_solver (default LP_SOLVER_CHOLESKY)             */
+  int32_t reserved;        /* must be 0                                          */
 } lp_options;
 
 /* Fill *opt with the defaults: alpha 0.95, FP64, no tape, switch gap 1e-6,

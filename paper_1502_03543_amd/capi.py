@@ -37,6 +37,10 @@ LP_PREC_MIXED = 1
 LP_METHOD_AFFINE = 0
 LP_METHOD_PC = 1
 
+# lp_solver
+LP_SOLVER_CHOLESKY = 0
+LP_SOLVER_WOODBURY = 1
+
 
 class lp_options(C.Structure):
     _fields_ = [
@@ -51,6 +55,8 @@ class lp_options(C.Structure):
         ("syrk_splits", C.c_int32),
         ("syrk32_splits", C.c_int32),
         ("method", C.c_int32),
+        ("solver", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

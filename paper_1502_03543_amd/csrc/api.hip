@@ -101,6 +101,11 @@ struct lp_handle {
   double* pcq = nullptr;                  // (dx_aff o ds_aff - sigma mu) / s
   double* amin = nullptr;                 // per-block steps to the boundary
   double* mupart = nullptr;               // per-block partials of mu_aff
+  // the paper's Woodbury / Egidi-Maponi solver (lp_options.solver)
+  bool woodbury = false;
+  double* wb_y0 = nullptr;  // (A A^T)^-1 A, columns contiguous
+  double* wb_x0 = nullptr;  // (A A^T)^-1 rhs of the current iteration
+  double* wb_one = nullptr; // n ones (A A^T as the normal matrix with D = I)
   // phase timing (lp_options.profile)
   enum { EV_ITER0, EV_SYRK0, EV_SYRKK0, EV_SYRKK1, EV_SYRK1, EV_CHOL1, EV_TRSV1, EV_ITER1, EV_N };
   hipEvent_t ev[EV_N] = {};
@@ -172,6 +177,11 @@ void carve(lp_handle* h, Carver& cv) {
     h->vtmp = cv.take<double>(n);
     h->rnorms = cv.take<double>(4);
   }
+  if (h->opt.solver == LP_SOLVER_WOODBURY) {
+    h->wb_y0 = cv.take<double>((size_t)m * n);
+    h->wb_x0 = cv.take<double>(m);
+    h->wb_one = cv.take<double>(n);
+  }
   if (h->opt.method == LP_METHOD_PC) {
     h->dxa = cv.take<double>(n);
     h->dsa = cv.take<double>(n);
@@ -216,6 +226,11 @@ bool valid_opts(const lp_options* o) {
       o->syrk32_splits > 64)
     return false;
   if (o->method != LP_METHOD_AFFINE && o->method != LP_METHOD_PC) return false;
+  if (o->solver != LP_SOLVER_CHOLESKY && o->solver != LP_SOLVER_WOODBURY) return false;
+  if (o->reserved != 0) return false;
+  if (o->solver == LP_SOLVER_WOODBURY &&
+      (o->precision != LP_PREC_FP64 || o->method != LP_METHOD_AFFINE || o->tape_capacity != 0))
+    return false;
   // the predictor-corrector runs in FP64 and has no reverse mode
   if (o->method == LP_METHOD_PC && (o->precision != LP_PREC_FP64 || o->tape_capacity != 0))
     return false;
@@ -266,6 +281,7 @@ lp_status lp_workspace_size(int64_t m, int64_t n, const lp_options* opt, size_t*
   lp_options_default(&o);
   if (opt) o = *opt;
   if (!valid_opts(&o)) return LP_ERR_INVALID_ARG;
+  if (o.solver == LP_SOLVER_WOODBURY && !woodbury_fits(m, n)) return LP_ERR_SHAPE;
   lp_handle h;
   h.m = m;
   h.n = n;
@@ -345,6 +361,31 @@ lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const
   h->gap = gap;
   h->k = 0;
   h->tape_len = 0;
+  if (h->opt.solver == LP_SOLVER_WOODBURY) {
+    // once: the factor of A A^T (kept in M) and (A A^T)^-1 A
+    h->woodbury = true;
+    e = woodbury_prepare();
+    if (e == hipSuccess) {
+      launch_wb_fill(s, n, 1.0, h->wb_one);
+      launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
+      launch_syrk_f64(s, (int)m, (int)n, A, n, h->wb_one, h->M, h->ldm, false, h->syrk_tile,
+                      h->syrk_splits, h->syrk_part);
+      launch_potrf_f64(s, (int)m, (int)m, h->M, h->ldm, h->info, h->diag);
+      launch_wb_cols(s, (int)m, (int)n, h->M, h->ldm, A, h->wb_y0);
+      DevInfo di{};
+      e = hipMemcpyAsync(&di, h->info, sizeof(di), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e == hipSuccess && di.chol_fail != INT_MAX) {
+        delete h;
+        return LP_ERR_BREAKDOWN;  // A A^T not positive definite: A rank-deficient
+      }
+    }
+    if (e != hipSuccess) {
+      delete h;
+      return LP_ERR_DEVICE;
+    }
+  }
   if (h->opt.profile) {
     h->profiling = true;
     for (int i = 0; i < lp_handle::EV_N; ++i) {
@@ -389,6 +430,20 @@ static void solve_fp64(lp_handle* h) {
   launch_potrf_f64(s, (int)m + 1, (int)m, h->M, h->ldm, h->info, h->diag);
   mark(h, lp_handle::EV_CHOL1);
   launch_trsv_bwd(s, (int)m, h->M, h->ldm, zrow, h->dy, h->trsv_sync, h->info);
+  h->last_prec = LP_PREC_FP64;
+}
+
+// The paper's Section 5 direction: x0 = (A A^T)^-1 rhs with the factor of
+// A A^T kept in M since setup, then the Egidi-Maponi recurrence over the n
+// rank-one terms (d_l - 1) a_l a_l^T.
+static void solve_woodbury(lp_handle* h) {
+  const long m = h->m, n = h->n;
+  hipStream_t s = h->st;
+  mark(h, lp_handle::EV_SYRK1);
+  launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
+  launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->wb_x0, h->trsv_sync, h->info);
+  launch_woodbury(s, (int)m, (int)n, h->A, h->d, h->wb_y0, h->wb_x0, h->dy, h->info);
+  mark(h, lp_handle::EV_CHOL1);
   h->last_prec = LP_PREC_FP64;
 }
 
@@ -532,7 +587,10 @@ static bool enqueue_iteration(lp_handle* h) {
       launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
     }
   }
-  if (!done) solve_fp64(h);
+  if (!done) {
+    if (h->woodbury) solve_woodbury(h);
+    else solve_fp64(h);
+  }
   mark(h, lp_handle::EV_TRSV1);
   launch_gemv_t(s, m, n, h->A, h->dy, h->y[cur], h->P1, h->P2);
   launch_dir(s, m, n, h->P1, h->P2, h->nchunks, h->rd[cur], h->x[cur], h->s[cur], h->d, h->dx,

@@ -143,6 +143,19 @@ void launch_trsv_fwd(hipStream_t st, int m, const double* L, long ld, const doub
 void launch_trsv_bwd(hipStream_t st, int m, const double* L, long ld, const double* z, double* y,
                      int* sync, DevInfo* info);
 
+// --- the paper's Woodbury / Egidi-Maponi solver (kernels_woodbury.hip) ------
+constexpr size_t kWoodburyMaxLds = 160 * 1024;  // one workgroup's LDS on gfx950
+size_t woodbury_lds_bytes(long m, long n);
+bool woodbury_fits(long m, long n);
+hipError_t woodbury_prepare();  // allows the kernel its dynamic LDS
+void launch_wb_fill(hipStream_t st, long n, double v, double* p);
+// Y0 = (L L^T)^-1 A, columns contiguous (Y0[k m + i]); L lower, row-major, ld
+void launch_wb_cols(hipStream_t st, int m, int n, const double* L, long ld, const double* A,
+                    double* Y0);
+// dy = (A D A^T)^-1 rhs from x0 = (A A^T)^-1 rhs by the rank-one recurrence
+void launch_woodbury(hipStream_t st, int m, int n, const double* A, const double* d,
+                     const double* Y0, const double* x0, double* dy, DevInfo* info);
+
 // --- reverse mode (kernels_adjoint.hip) -------------------------------------
 void launch_zero(hipStream_t st, double* p, long count);
 void launch_adj_tbar(hipStream_t st, long m, long n, const double* xb, const double* dx,

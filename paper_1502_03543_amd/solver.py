@@ -14,6 +14,7 @@ from . import capi
 
 _PREC = {"fp64": capi.LP_PREC_FP64, "mixed": capi.LP_PREC_MIXED}
 _METHOD = {"affine": capi.LP_METHOD_AFFINE, "pc": capi.LP_METHOD_PC}
+_SOLVER = {"cholesky": capi.LP_SOLVER_CHOLESKY, "woodbury": capi.LP_SOLVER_WOODBURY}
 
 
 def _p(t):
@@ -42,7 +43,7 @@ def workspace(nbytes: int, device) -> tuple[torch.Tensor, int]:
 
 def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6,
             refine_tol=2.0 ** -46, refine_max=5, profile=False, syrk_tile=0, syrk_splits=0,
-            syrk32_splits=0, method="affine") -> capi.lp_options:
+            syrk32_splits=0, method="affine", solver="cholesky") -> capi.lp_options:
     o = capi.lp_options()
     capi.lp_options_default(C.byref(o))
     o.alpha = float(alpha)
@@ -56,6 +57,7 @@ def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6
     o.syrk_splits = int(syrk_splits)
     o.syrk32_splits = int(syrk32_splits)
     o.method = _METHOD[method]
+    o.solver = _SOLVER[solver]
     return o
 
 

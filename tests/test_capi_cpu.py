@@ -74,3 +74,23 @@ def test_method_validation():
     m = (C.c_int64 * 2)(16, 20)
     n = (C.c_int64 * 2)(40, 60)
     assert capi.lp_batch_workspace_size(2, m, n, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+
+
+def test_solver_validation():
+    """LP_SOLVER_WOODBURY: FP64, Section 3 method, no tape, and a problem whose
+    recurrence fits one workgroup's LDS."""
+    o = capi.lp_options()
+    capi.lp_options_default(C.byref(o))
+    assert o.solver == capi.LP_SOLVER_CHOLESKY and o.reserved == 0
+    sz = C.c_size_t(0)
+    o.solver = capi.LP_SOLVER_WOODBURY
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_OK
+    assert capi.lp_workspace_size(128, 1024, C.byref(o), C.byref(sz)) == capi.LP_ERR_SHAPE
+    for field, value in (("precision", capi.LP_PREC_MIXED), ("method", capi.LP_METHOD_PC),
+                         ("tape_capacity", 2), ("reserved", 1)):
+        old = getattr(o, field)
+        setattr(o, field, value)
+        assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+        setattr(o, field, old)
+    o.solver = 2
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
