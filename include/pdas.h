@@ -89,7 +89,7 @@ typedef enum lp_solver {
                              (A A^T)^-1 [A | rhs] (factor of A A^T and
                              (A A^T)^-1 A formed once at lp_setup).  The n terms
                              run in one workgroup with Y in LDS, so it needs
-                             8 ((n + 1) ld + 2 m) <= 160 KiB, ld = m rounded up
+                             8 ((n + 1) ld + n + 16 m) <= 160 KiB, ld = m rounded up
                              to odd (LP_ERR_SHAPE otherwise: e.g. m = 64,
                              n = 256 fits); FP64, LP_METHOD_AFFINE, no tape
                              (LP_ERR_INVALID_ARG otherwise).  A rank-deficient

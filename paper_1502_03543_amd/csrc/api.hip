@@ -439,6 +439,10 @@ static void solve_fp64(lp_handle* h) {
 static void solve_woodbury(lp_handle* h) {
   const long m = h->m, n = h->n;
   hipStream_t s = h->st;
+  // no normal matrix in this solver: its phase events are recorded empty,
+  // so that every event of the iteration's timing has been recorded
+  mark(h, lp_handle::EV_SYRKK0);
+  mark(h, lp_handle::EV_SYRKK1);
   mark(h, lp_handle::EV_SYRK1);
   launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
   launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->wb_x0, h->trsv_sync, h->info);

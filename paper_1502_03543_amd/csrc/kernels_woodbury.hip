@@ -16,7 +16,9 @@
 // distinct banks), so each term costs one barrier and no global traffic:
 // the workgroup's threads take the columns k > l in turn, and every thread
 // forms den_l itself from the broadcast column y_l and a_l (staged in LDS
-// one term ahead), so all take the same breakdown decision.  The paper
+// in blocks of terms), so all take the same breakdown decision.  The chain
+// is bound by LDS instruction issue (about 5m accesses per column and
+// term), not by arithmetic.  The paper
 // assigns one CUDA block per column and launches a kernel per term; on
 // this chip one compute unit running the whole chain avoids n grid-wide
 // synchronisations, and the LDS (160 KB) bounds the problem size.
@@ -60,7 +62,26 @@ __global__ void k_wb_fill(long n, double v, double* __restrict__ p) {
 // The recurrence for one iteration: Y0 (column-major, m x n), x0 (m), d (n)
 // in; dy = x_n out.  A term whose denominator is not a finite positive
 // number records its index as the breakdown column; the smallest
-// denominator is reported like a pivot.
+// denominator is reported like a pivot.  d is staged in LDS once, and the
+// columns a_l of A in blocks of kWbBlk terms, so a term waits on no global
+// load; the inner products run as four interleaved partial sums (a fixed
+// order), which shortens their dependency chains.
+constexpr int kWbBlk = 16;
+
+__device__ __forceinline__ double dot4(int m, const double* __restrict__ a,
+                                       const double* __restrict__ b) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 4 <= m; i += 4) {
+    s0 += a[i] * b[i];
+    s1 += a[i + 1] * b[i + 1];
+    s2 += a[i + 2] * b[i + 2];
+    s3 += a[i + 3] * b[i + 3];
+  }
+  for (; i < m; ++i) s0 += a[i] * b[i];
+  return (s0 + s1) + (s2 + s3);
+}
+
 __global__ __launch_bounds__(kWbThreads) void k_woodbury(int m, int n,
                                                           const double* __restrict__ A,
                                                           const double* __restrict__ d,
@@ -71,29 +92,33 @@ __global__ __launch_bounds__(kWbThreads) void k_woodbury(int m, int n,
   extern __shared__ double lds[];
   const int ld = wb_ld(m);
   double* Ys = lds;                        // n + 1 columns: y_0 .. y_{n-1}, then x
-  double* sa = Ys + (long)(n + 1) * ld;    // a_l, two buffers of m
+  double* sd = Ys + (long)(n + 1) * ld;    // d
+  double* sa = sd + n;                     // a_l of the current block, column l at l % kWbBlk
   const int tid = threadIdx.x;
   for (long e = tid; e < (long)n * m; e += kWbThreads) {
     const long k = e / m, i = e - k * m;
     Ys[k * ld + i] = Y0[e];
   }
-  for (int i = tid; i < m; i += kWbThreads) {
-    Ys[(long)n * ld + i] = x0[i];
-    sa[i] = A[(long)i * n];
-  }
-  __syncthreads();
+  for (int i = tid; i < m; i += kWbThreads) Ys[(long)n * ld + i] = x0[i];
+  for (int j = tid; j < n; j += kWbThreads) sd[j] = d[j];
   double minden = INFINITY;
   int fail = -1;
   for (int l = 0; l < n; ++l) {
-    const double* al = sa + (l & 1) * m;
-    if (l + 1 < n)
-      for (int i = tid; i < m; i += kWbThreads) sa[((l + 1) & 1) * m + i] = A[(long)i * n + l + 1];
-    const double v = d[l] - 1.0;
+    if (l % kWbBlk == 0) {
+      // the next block of columns of A (the previous block is no longer read:
+      // every thread passed the barrier that ended its last term)
+      const int nb = min(kWbBlk, n - l);
+      for (int e = tid; e < nb * m; e += kWbThreads) {
+        const int c = e / m, i = e - c * m;
+        sa[c * m + i] = A[(long)i * n + l + c];
+      }
+      __syncthreads();
+    }
+    const double* al = sa + (l % kWbBlk) * m;
+    const double v = sd[l] - 1.0;
     if (v != 0.0) {
       const double* yl = Ys + (long)l * ld;
-      double dl = 0.0;
-      for (int i = 0; i < m; ++i) dl += al[i] * yl[i];
-      const double den = 1.0 + v * dl;
+      const double den = 1.0 + v * dot4(m, al, yl);
       if (!(den > 0.0) || !isfinite(den)) {
         fail = l;  // every thread computed the same den: a uniform exit
         break;
@@ -102,9 +127,7 @@ __global__ __launch_bounds__(kWbThreads) void k_woodbury(int m, int n,
       const double f = v / den;
       for (int k = l + 1 + tid; k <= n; k += kWbThreads) {
         double* yk = Ys + (long)k * ld;
-        double dk = 0.0;
-        for (int i = 0; i < m; ++i) dk += al[i] * yk[i];
-        const double ck = f * dk;
+        const double ck = f * dot4(m, al, yk);
         for (int i = 0; i < m; ++i) yk[i] -= ck * yl[i];
       }
     }
@@ -124,7 +147,7 @@ __global__ __launch_bounds__(kWbThreads) void k_woodbury(int m, int n,
 
 size_t woodbury_lds_bytes(long m, long n) {
   const long ld = (m & 1) ? m : m + 1;
-  return (size_t)((n + 1) * ld + 2 * m) * sizeof(double);
+  return (size_t)((n + 1) * ld + n + (long)kWbBlk * m) * sizeof(double);
 }
 
 bool woodbury_fits(long m, long n) { return woodbury_lds_bytes(m, n) <= kWoodburyMaxLds; }
