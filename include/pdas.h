@@ -195,6 +195,39 @@ lp_status lp_setup(lp_handle** h, int64_t m, int64_t n, const double* A, const d
                    const lp_options* opt, void* workspace, size_t ws_bytes,
                    lp_stream_t stream);
 
+/* Sparse A (Section 7 names sparse systems as the method's next step, with
+ * coalesced access as the difficulty).  A is given in canonical CSR: row_ptr
+ * (device, m + 1 int64: row_ptr[0] = 0, non-decreasing, row_ptr[m] = nnz),
+ * col_idx (device, nnz int32, strictly increasing within each row: sorted,
+ * no duplicates, in [0, n)), vals (device, nnz doubles, finite).  The three
+ * arrays are borrowed like A in lp_setup.  The library builds the transpose
+ * (CSC) once in the workspace; the products A w and A^T v then run on the
+ * CSR and the CSC, the normal matrix A D A^T on both (its dense lower
+ * triangle: the Cholesky, the triangular solves and every vector kernel are
+ * those of the dense path, and so are the results up to the rounding order
+ * of the sums).  Supported: FP64, LP_SOLVER_CHOLESKY, LP_METHOD_AFFINE and
+ * LP_METHOD_PC, no tape; other options give LP_ERR_INVALID_ARG.  The
+ * normal-matrix kernel keeps one row of M in LDS, so m <= LP_CSR_MAX_M
+ * (LP_ERR_SHAPE above).  nnz = 0 is accepted (the first iteration then
+ * reports LP_ERR_BREAKDOWN). */
+#define LP_CSR_MAX_M 16384
+
+/* Workspace bytes for lp_setup_csr.  Errors: LP_ERR_SHAPE (as lp_workspace_size,
+ * m > LP_CSR_MAX_M, nnz < 0 or nnz > INT32_MAX), LP_ERR_INVALID_ARG. */
+lp_status lp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, const lp_options* opt,
+                                size_t* bytes);
+
+/* lp_setup for a CSR matrix A.  Validates on the device what lp_setup does,
+ * and the CSR structure and values (LP_ERR_INVALID_ARG when they break the
+ * rules above).  The returned handle takes lp_iterate, lp_solve,
+ * lp_get_iterate, lp_get_direction, lp_get_timings and lp_destroy;
+ * lp_backward returns LP_ERR_NO_TAPE.  Synchronises the stream. */
+lp_status lp_setup_csr(lp_handle** h, int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                       const int32_t* col_idx, const double* vals, const double* b,
+                       const double* c, const double* x0, const double* y0, const double* s0,
+                       const lp_options* opt, void* workspace, size_t ws_bytes,
+                       lp_stream_t stream);
+
 /* One pass of the Section 3 loop body: direction, zero-direction test, ratio
  * test, psi == 1 rule, step.  Returns LP_OK to continue, LP_OPTIMAL_PSI1,
  * LP_OPTIMAL_ZERO_DIR or an error.  info (host, nullable) receives the
@@ -356,6 +389,21 @@ lp_status lp_cholesky(int64_t m, double* M, int64_t ldm, void* workspace, size_t
  * (may not alias).  Stream-ordered, does not synchronise. */
 lp_status lp_chol_solve(int64_t m, const double* L, int64_t ldm, const double* r, double* dy,
                         void* workspace, size_t ws_bytes, lp_stream_t stream);
+
+/* Workspace bytes for lp_normal_matrix_csr (the CSC of A and its index maps). */
+lp_status lp_csr_workspace_size(int64_t m, int64_t n, int64_t nnz, size_t* bytes);
+
+/* lp_normal_matrix for A in canonical CSR (rules as lp_setup_csr): M = A
+ * diag(d) A^T written to the lower triangle (i >= j) of M (device,
+ * row-major, ldm >= m), with the kernel lp_setup_csr's handle uses.
+ * Checks the CSR on the device and builds its transpose in the workspace on
+ * every call (LP_ERR_INVALID_ARG for a bad structure or value), so it
+ * synchronises.  Errors: LP_ERR_SHAPE (m < 1, n < 1, m > LP_CSR_MAX_M, nnz
+ * out of range), LP_ERR_WORKSPACE, LP_ERR_DEVICE. */
+lp_status lp_normal_matrix_csr(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col_idx, const double* vals, const double* d,
+                               double* M, int64_t ldm, void* workspace, size_t ws_bytes,
+                               lp_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* Allocation-free entry point                                                 */

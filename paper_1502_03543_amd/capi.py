@@ -123,6 +123,13 @@ def _signatures(lib):
         "lp_workspace_size": (_st, [_i64, _i64, C.POINTER(lp_options), C.POINTER(C.c_size_t)]),
         "lp_setup": (_st, [C.POINTER(P), _i64, _i64, P, P, P, P, P, P, C.POINTER(lp_options), P,
                            C.c_size_t, P]),
+        "lp_workspace_size_csr": (_st, [_i64, _i64, _i64, C.POINTER(lp_options),
+                                        C.POINTER(C.c_size_t)]),
+        "lp_setup_csr": (_st, [C.POINTER(P), _i64, _i64, _i64, P, P, P, P, P, P, P, P,
+                               C.POINTER(lp_options), P, C.c_size_t, P]),
+        "lp_csr_workspace_size": (_st, [_i64, _i64, _i64, C.POINTER(C.c_size_t)]),
+        "lp_normal_matrix_csr": (_st, [_i64, _i64, _i64, P, P, P, P, P, _i64, P, C.c_size_t,
+                                       P]),
         "lp_iterate": (_st, [P, C.POINTER(lp_iter_info)]),
         "lp_solve": (_st, [P, C.c_double, C.c_int32, C.POINTER(lp_result),
                            C.POINTER(lp_iter_info)]),
@@ -147,6 +154,7 @@ def _signatures(lib):
         "lp_batch_get_iterate": (_st, [P, P, P, P]),
         "lp_batch_backward": (_st, [P, P, P, P, P, P, P, P, P, P]),
         "lp_batch_destroy": (_st, [P]),
+        "lp_chol_solve_noalloc": (_st, [_i64, P, _i64, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name, None)
@@ -199,6 +207,10 @@ lp_options_default = _fn("lp_options_default")
 lp_status_string = _fn("lp_status_string")
 lp_workspace_size = _fn("lp_workspace_size")
 lp_setup = _fn("lp_setup")
+lp_workspace_size_csr = _fn("lp_workspace_size_csr")
+lp_setup_csr = _fn("lp_setup_csr")
+lp_csr_workspace_size = _fn("lp_csr_workspace_size")
+lp_normal_matrix_csr = _fn("lp_normal_matrix_csr")
 lp_iterate = _fn("lp_iterate")
 lp_solve = _fn("lp_solve")
 lp_get_iterate = _fn("lp_get_iterate")

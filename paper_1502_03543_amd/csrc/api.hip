@@ -106,6 +106,16 @@ struct lp_handle {
   double* wb_y0 = nullptr;  // (A A^T)^-1 A, columns contiguous
   double* wb_x0 = nullptr;  // (A A^T)^-1 rhs of the current iteration
   double* wb_one = nullptr; // n ones (A A^T as the normal matrix with D = I)
+  // sparse A (lp_setup_csr): the caller's CSR and the CSC built from it
+  bool sp = false;
+  long nnz = 0;
+  const int64_t* rp = nullptr;
+  const int* ci = nullptr;
+  const double* av = nullptr;
+  int64_t* cp = nullptr;
+  int *ri = nullptr, *smap = nullptr, *ssrc = nullptr, *scnt = nullptr, *scur = nullptr;
+  double* cv = nullptr;
+  int* sflags = nullptr;
   // phase timing (lp_options.profile)
   enum { EV_ITER0, EV_SYRK0, EV_SYRKK0, EV_SYRKK1, EV_SYRK1, EV_CHOL1, EV_TRSV1, EV_ITER1, EV_N };
   hipEvent_t ev[EV_N] = {};
@@ -114,6 +124,36 @@ struct lp_handle {
 };
 
 namespace {
+
+struct Csc {
+  int64_t* cp;
+  int *ri, *map, *src, *cnt, *cur, *flags;
+  double* cv;
+};
+
+void carve_csc(long n, long nnz, Carver& cv, Csc& c) {
+  c.cp = cv.take<int64_t>(n + 1);
+  c.ri = cv.take<int>(nnz > 0 ? nnz : 1);
+  c.cv = cv.take<double>(nnz > 0 ? nnz : 1);
+  c.map = cv.take<int>(nnz > 0 ? nnz : 1);
+  c.src = cv.take<int>(nnz > 0 ? nnz : 1);
+  c.cnt = cv.take<int>(n);
+  c.cur = cv.take<int>(n);
+  c.flags = cv.take<int>(4);
+}
+
+void carve_csc(lp_handle* h, Carver& cv) {
+  Csc c;
+  carve_csc(h->n, h->nnz, cv, c);
+  h->cp = c.cp;
+  h->ri = c.ri;
+  h->cv = c.cv;
+  h->smap = c.map;
+  h->ssrc = c.src;
+  h->scnt = c.cnt;
+  h->scur = c.cur;
+  h->sflags = c.flags;
+}
 
 void carve(lp_handle* h, Carver& cv) {
   const long m = h->m, n = h->n;
@@ -144,9 +184,9 @@ void carve(lp_handle* h, Carver& cv) {
     if (h->syrk_tile == 0) h->syrk_tile = 128;
     h->syrk_splits = h->opt.syrk_splits;
   }
-  h->syrk_part_n = syrk_part_elems((int)m, h->syrk_tile, h->syrk_splits);
+  h->syrk_part_n = h->sp ? 0 : syrk_part_elems((int)m, h->syrk_tile, h->syrk_splits);
   h->syrk_part = h->syrk_part_n ? cv.take<double>(h->syrk_part_n) : nullptr;
-  h->nchunks = gemv_t_chunks(m);
+  h->nchunks = h->sp ? 1 : gemv_t_chunks(m);  // the sparse A^T product sums in full
   h->P1 = cv.take<double>((size_t)h->nchunks * n);
   h->P2 = cv.take<double>((size_t)h->nchunks * n);
   h->ndir = dir_blocks(n);
@@ -177,6 +217,7 @@ void carve(lp_handle* h, Carver& cv) {
     h->vtmp = cv.take<double>(n);
     h->rnorms = cv.take<double>(4);
   }
+  if (h->sp) carve_csc(h, cv);
   if (h->opt.solver == LP_SOLVER_WOODBURY) {
     h->wb_y0 = cv.take<double>((size_t)m * n);
     h->wb_x0 = cv.take<double>(m);
@@ -274,51 +315,81 @@ const char* lp_status_string(int32_t s) {
   }
 }
 
-lp_status lp_workspace_size(int64_t m, int64_t n, const lp_options* opt, size_t* bytes) {
+// Shape, option and workspace rules shared by the dense and the CSR setup.
+static lp_status workspace_size_impl(int64_t m, int64_t n, bool sparse, int64_t nnz,
+                                     const lp_options* opt, size_t* bytes) {
   if (!bytes) return LP_ERR_INVALID_ARG;
   if (m < 1 || n <= m || m > INT_MAX / 2 || n > INT_MAX / 2) return LP_ERR_SHAPE;
+  if (sparse && (m > LP_CSR_MAX_M || !sp_fits(m) || nnz < 0 || nnz > INT_MAX))
+    return LP_ERR_SHAPE;
   lp_options o;
   lp_options_default(&o);
   if (opt) o = *opt;
   if (!valid_opts(&o)) return LP_ERR_INVALID_ARG;
+  // the sparse path: FP64 Cholesky, no tape (affine or predictor-corrector)
+  if (sparse && (o.precision != LP_PREC_FP64 || o.solver != LP_SOLVER_CHOLESKY ||
+                 o.tape_capacity != 0))
+    return LP_ERR_INVALID_ARG;
   if (o.solver == LP_SOLVER_WOODBURY && !woodbury_fits(m, n)) return LP_ERR_SHAPE;
   lp_handle h;
   h.m = m;
   h.n = n;
   h.opt = o;
+  h.sp = sparse;
+  h.nnz = sparse ? nnz : 0;
   Carver cv(nullptr);
   carve(&h, cv);
   *bytes = (cv.off + kAlign - 1) / kAlign * kAlign;
   return LP_OK;
 }
 
-lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const double* b,
-                   const double* c, const double* x0, const double* y0, const double* s0,
-                   const lp_options* opt, void* workspace, size_t ws_bytes, lp_stream_t stream) {
-  if (!out) return LP_ERR_INVALID_ARG;
-  *out = nullptr;
-  size_t need = 0;
-  lp_status st = lp_workspace_size(m, n, opt, &need);
-  if (st != LP_OK) return st;
-  if (!A || !b || !c || !x0 || !y0 || !s0) return LP_ERR_INVALID_ARG;
-  if (!workspace || ws_bytes < need || ((uintptr_t)workspace % kAlign) != 0)
-    return LP_ERR_WORKSPACE;
-  lp_handle* h = new (std::nothrow) lp_handle();
-  if (!h) return LP_ERR_INVALID_ARG;
-  h->m = m;
-  h->n = n;
-  lp_options_default(&h->opt);
-  if (opt) h->opt = *opt;
-  h->st = reinterpret_cast<hipStream_t>(stream);
-  h->A = A;
-  Carver cv(workspace);
-  carve(h, cv);
-  hipStream_t s = h->st;
+// Checks A's CSR on the device (structure, finiteness) and builds the CSC;
+// synchronises.  LP_ERR_INVALID_ARG for a bad CSR.
+static lp_status csr_prepare(hipStream_t s, long m, long n, long nnz, const int64_t* rp,
+                             const int* ci, const double* v, int* flags, int64_t* cp, int* ri,
+                             double* cv, int* src, int* map, int* cnt, int* cur) {
+  launch_fill_i32(s, flags, 0, 4);
+  launch_sp_check(s, m, n, nnz, rp, ci, v, flags);
+  int hf[4] = {};
+  hipError_t e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return LP_ERR_DEVICE;
+  if (hf[0]) return LP_ERR_INVALID_ARG;
+  e = sp_prepare();
+  if (e != hipSuccess) return LP_ERR_DEVICE;
+  launch_sp_transpose(s, m, n, nnz, rp, ci, v, cnt, cur, cp, ri, cv, src, map);
+  e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  return e == hipSuccess ? LP_OK : LP_ERR_DEVICE;
+}
 
+// A^T v1 (and A^T v2) into the handle's partial sums P1 (P2), dense or CSC.
+static void apply_At(lp_handle* h, const double* v1, const double* v2) {
+  if (h->sp)
+    launch_sp_gemv_t(h->st, h->n, h->nnz, h->cp, h->ri, h->cv, v1, v2, h->P1, v2 ? h->P2 : nullptr);
+  else
+    launch_gemv_t(h->st, h->m, h->n, h->A, v1, v2, h->P1, v2 ? h->P2 : nullptr);
+}
+
+// out = base + sign * A w, dense or CSR.
+static void apply_A(lp_handle* h, const double* w, const double* base, double* out,
+                    double sign = 1.0) {
+  if (h->sp) launch_sp_gemv_n(h->st, h->m, h->nnz, h->rp, h->ci, h->av, w, base, out, sign);
+  else launch_gemv_n(h->st, h->m, h->n, h->A, w, base, out, sign);
+}
+
+// Everything after the carve: device validation, copies, r_d, gap, the
+// Woodbury preparation and the profiling events.  Deletes h on error.
+static lp_status setup_finish(lp_handle* h, const double* b, const double* c, const double* x0,
+                              const double* y0, const double* s0) {
+  const long m = h->m, n = h->n;
+  hipStream_t s = h->st;
+  lp_status st = LP_OK;
   // validation on the device: finiteness and interior start
   hipError_t e = hipMemsetAsync(h->chk, 0, sizeof(DevCheck), s);
   if (e == hipSuccess) {
-    launch_check_inputs(s, m, n, A, b, c, x0, y0, s0, h->chk);
+    launch_check_inputs(s, m, n, h->A, b, c, x0, y0, s0, h->chk);  // A null when sparse
     DevCheck chk{};
     e = hipMemcpyAsync(&chk, h->chk, sizeof(chk), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -327,6 +398,9 @@ lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const
     else if (e == hipSuccess && chk.nonpos) st = LP_ERR_NOT_INTERIOR;
   }
   if (e != hipSuccess) st = LP_ERR_DEVICE;
+  if (st == LP_OK && h->sp)
+    st = csr_prepare(s, m, n, h->nnz, h->rp, h->ci, h->av, h->sflags, h->cp, h->ri, h->cv,
+                     h->ssrc, h->smap, h->scnt, h->scur);
   if (st != LP_OK) {
     delete h;
     return st;
@@ -343,11 +417,11 @@ lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const
   if (h->opt.precision == LP_PREC_MIXED) {
     h->mixed = true;
     h->fp32_mode = true;
-    launch_to_f32(s, m * n, A, h->A32);
-    launch_colsq(s, m, n, A, h->colsq);
+    launch_to_f32(s, m * n, h->A, h->A32);
+    launch_colsq(s, m, n, h->A, h->colsq);
   }
   // r_d = c - A^T y0 - s0
-  launch_gemv_t(s, m, n, A, h->y[0], nullptr, h->P1, nullptr);
+  apply_At(h, h->y[0], nullptr);
   launch_dual_resid(s, m, n, h->P1, h->nchunks, h->c, h->s[0], h->rd[0]);
   launch_gap(s, n, h->x[0], h->s[0], h->gap_part, h->gap_dev);
   double gap = 0;
@@ -368,10 +442,10 @@ lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const
     if (e == hipSuccess) {
       launch_wb_fill(s, n, 1.0, h->wb_one);
       launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
-      launch_syrk_f64(s, (int)m, (int)n, A, n, h->wb_one, h->M, h->ldm, false, h->syrk_tile,
+      launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->wb_one, h->M, h->ldm, false, h->syrk_tile,
                       h->syrk_splits, h->syrk_part);
       launch_potrf_f64(s, (int)m, (int)m, h->M, h->ldm, h->info, h->diag);
-      launch_wb_cols(s, (int)m, (int)n, h->M, h->ldm, A, h->wb_y0);
+      launch_wb_cols(s, (int)m, (int)n, h->M, h->ldm, h->A, h->wb_y0);
       DevInfo di{};
       e = hipMemcpyAsync(&di, h->info, sizeof(di), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -395,8 +469,75 @@ lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const
       }
     }
   }
-  *out = h;
   return LP_OK;
+}
+
+lp_status lp_workspace_size(int64_t m, int64_t n, const lp_options* opt, size_t* bytes) {
+  return workspace_size_impl(m, n, false, 0, opt, bytes);
+}
+
+lp_status lp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, const lp_options* opt,
+                                size_t* bytes) {
+  return workspace_size_impl(m, n, true, nnz, opt, bytes);
+}
+
+lp_status lp_setup(lp_handle** out, int64_t m, int64_t n, const double* A, const double* b,
+                   const double* c, const double* x0, const double* y0, const double* s0,
+                   const lp_options* opt, void* workspace, size_t ws_bytes, lp_stream_t stream) {
+  if (!out) return LP_ERR_INVALID_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  lp_status st = lp_workspace_size(m, n, opt, &need);
+  if (st != LP_OK) return st;
+  if (!A || !b || !c || !x0 || !y0 || !s0) return LP_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < need || ((uintptr_t)workspace % kAlign) != 0)
+    return LP_ERR_WORKSPACE;
+  lp_handle* h = new (std::nothrow) lp_handle();
+  if (!h) return LP_ERR_INVALID_ARG;
+  h->m = m;
+  h->n = n;
+  lp_options_default(&h->opt);
+  if (opt) h->opt = *opt;
+  h->st = reinterpret_cast<hipStream_t>(stream);
+  h->A = A;
+  Carver cv(workspace);
+  carve(h, cv);
+  st = setup_finish(h, b, c, x0, y0, s0);
+  if (st == LP_OK) *out = h;
+  return st;
+}
+
+lp_status lp_setup_csr(lp_handle** out, int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                       const int32_t* col_idx, const double* vals, const double* b,
+                       const double* c, const double* x0, const double* y0, const double* s0,
+                       const lp_options* opt, void* workspace, size_t ws_bytes,
+                       lp_stream_t stream) {
+  if (!out) return LP_ERR_INVALID_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  lp_status st = lp_workspace_size_csr(m, n, nnz, opt, &need);
+  if (st != LP_OK) return st;
+  if (!row_ptr || (nnz > 0 && (!col_idx || !vals)) || !b || !c || !x0 || !y0 || !s0)
+    return LP_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < need || ((uintptr_t)workspace % kAlign) != 0)
+    return LP_ERR_WORKSPACE;
+  lp_handle* h = new (std::nothrow) lp_handle();
+  if (!h) return LP_ERR_INVALID_ARG;
+  h->m = m;
+  h->n = n;
+  lp_options_default(&h->opt);
+  if (opt) h->opt = *opt;
+  h->st = reinterpret_cast<hipStream_t>(stream);
+  h->sp = true;
+  h->nnz = nnz;
+  h->rp = row_ptr;
+  h->ci = col_idx;
+  h->av = vals;
+  Carver cv(workspace);
+  carve(h, cv);
+  st = setup_finish(h, b, c, x0, y0, s0);
+  if (st == LP_OK) *out = h;
+  return st;
 }
 
 static void record_tape(lp_handle* h) {
@@ -419,10 +560,16 @@ static void mark(lp_handle* h, int i) {
 static void solve_fp64(lp_handle* h) {
   const long m = h->m, n = h->n;
   hipStream_t s = h->st;
-  launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->d, h->M, h->ldm, false, h->syrk_tile,
-                  h->syrk_splits, h->syrk_part,
-                  h->profiling ? h->ev[lp_handle::EV_SYRKK0] : nullptr,
-                  h->profiling ? h->ev[lp_handle::EV_SYRKK1] : nullptr);
+  if (h->sp) {
+    mark(h, lp_handle::EV_SYRKK0);
+    launch_sp_syrk(s, m, h->rp, h->ci, h->av, h->cp, h->ri, h->cv, h->smap, h->d, h->M, h->ldm);
+    mark(h, lp_handle::EV_SYRKK1);
+  } else {
+    launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->d, h->M, h->ldm, false, h->syrk_tile,
+                    h->syrk_splits, h->syrk_part,
+                    h->profiling ? h->ev[lp_handle::EV_SYRKK0] : nullptr,
+                    h->profiling ? h->ev[lp_handle::EV_SYRKK1] : nullptr);
+  }
   mark(h, lp_handle::EV_SYRK1);
   // rhs rides along as row m of the factorization: it leaves as z = L^-1 rhs
   double* zrow = h->M + (size_t)m * h->ldm;
@@ -544,20 +691,20 @@ static void enqueue_pc_iteration(lp_handle* h) {
   mark(h, lp_handle::EV_ITER0);
   launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
   launch_prep(s, n, h->x[cur], h->s[cur], h->rd[cur], h->d, h->w);
-  launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
+  apply_A(h, h->w, h->b, h->rhs);
   mark(h, lp_handle::EV_SYRK0);
   solve_fp64(h);  // dy: the predictor
-  launch_gemv_t(s, m, n, h->A, h->dy, h->y[cur], h->P1, h->P2);
+  apply_At(h, h->dy, h->y[cur]);
   launch_pc_aff(s, n, h->P1, h->P2, h->nchunks, h->rd[cur], h->x[cur], h->s[cur], h->d, h->dxa,
                 h->dsa, h->gy, h->amin);
   launch_pc_corr(s, n, h->gap, h->amin, h->x[cur], h->s[cur], h->rd[cur], h->d, h->dxa, h->dsa,
                  h->mupart, h->pcq, h->w, h->info);
-  launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
+  apply_A(h, h->w, h->b, h->rhs);
   launch_fill_i32(s, h->trsv_sync, 0, 4 + 2 * h->nblk);
   launch_trsv_fwd(s, (int)m, h->M, h->ldm, h->rhs, h->z, h->trsv_sync, h->info);
   launch_trsv_bwd(s, (int)m, h->M, h->ldm, h->z, h->dy, h->trsv_sync, h->info);
   mark(h, lp_handle::EV_TRSV1);
-  launch_gemv_t(s, m, n, h->A, h->dy, nullptr, h->P1, nullptr);
+  apply_At(h, h->dy, nullptr);
   launch_pc_dir(s, n, h->P1, h->nchunks, h->rd[cur], h->x[cur], h->s[cur], h->d, h->pcq, h->dx,
                 h->ds, h->g, h->amin, h->zpart, h->npart);
   launch_pc_step(s, m, n, h->opt.alpha, h->amin, h->zpart, h->npart, h->dy, h->x[cur], h->y[cur],
@@ -581,7 +728,7 @@ static bool enqueue_iteration(lp_handle* h) {
   launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
   launch_prep(s, n, h->x[cur], h->s[cur], h->rd[cur], h->d, h->w,
               h->fp32_mode ? h->sd32 : nullptr);
-  launch_gemv_n(s, m, n, h->A, h->w, h->b, h->rhs);
+  apply_A(h, h->w, h->b, h->rhs);
   mark(h, lp_handle::EV_SYRK0);
   bool done = false;
   if (h->fp32_mode) {
@@ -596,7 +743,7 @@ static bool enqueue_iteration(lp_handle* h) {
     else solve_fp64(h);
   }
   mark(h, lp_handle::EV_TRSV1);
-  launch_gemv_t(s, m, n, h->A, h->dy, h->y[cur], h->P1, h->P2);
+  apply_At(h, h->dy, h->y[cur]);
   launch_dir(s, m, n, h->P1, h->P2, h->nchunks, h->rd[cur], h->x[cur], h->s[cur], h->d, h->dx,
              h->ds, h->gy, h->g, h->rpart, h->ipart, h->zpart, h->npart);
   launch_step(s, m, n, h->opt.alpha, h->ndir, h->rpart, h->ipart, h->zpart, h->npart, h->dy,
@@ -904,6 +1051,40 @@ lp_status lp_cholesky(int64_t m, double* M, int64_t ldm, void* workspace, size_t
   if (fail_col) *fail_col = broke ? di.chol_fail : -1;
   if (min_pivot) *min_pivot = di.min_pivot;
   return broke ? LP_ERR_BREAKDOWN : LP_OK;
+}
+
+lp_status lp_csr_workspace_size(int64_t m, int64_t n, int64_t nnz, size_t* bytes) {
+  if (!bytes) return LP_ERR_INVALID_ARG;
+  if (m < 1 || n < 1 || m > LP_CSR_MAX_M || !sp_fits(m) || n > INT_MAX / 2 || nnz < 0 ||
+      nnz > INT_MAX)
+    return LP_ERR_SHAPE;
+  Carver cv(nullptr);
+  Csc c;
+  carve_csc(n, nnz, cv, c);
+  *bytes = (cv.off + kAlign - 1) / kAlign * kAlign;
+  return LP_OK;
+}
+
+lp_status lp_normal_matrix_csr(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col_idx, const double* vals, const double* d,
+                               double* M, int64_t ldm, void* workspace, size_t ws_bytes,
+                               lp_stream_t stream) {
+  size_t need = 0;
+  lp_status st = lp_csr_workspace_size(m, n, nnz, &need);
+  if (st != LP_OK) return st;
+  if (!row_ptr || (nnz > 0 && (!col_idx || !vals)) || !d || !M || ldm < m)
+    return LP_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < need || ((uintptr_t)workspace % kAlign) != 0)
+    return LP_ERR_WORKSPACE;
+  Carver cv(workspace);
+  Csc c;
+  carve_csc(n, nnz, cv, c);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = csr_prepare(s, m, n, nnz, row_ptr, col_idx, vals, c.flags, c.cp, c.ri, c.cv, c.src, c.map,
+                   c.cnt, c.cur);
+  if (st != LP_OK) return st;
+  launch_sp_syrk(s, m, row_ptr, col_idx, vals, c.cp, c.ri, c.cv, c.map, d, M, ldm);
+  return hip_ok(hipGetLastError());
 }
 
 lp_status lp_chol_solve(int64_t m, const double* L, int64_t ldm, const double* r, double* dy,

@@ -68,7 +68,8 @@ __global__ void k_check_inputs(long m, long n, const double* A, const double* b,
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long stride = (long)gridDim.x * blockDim.x;
   int bad = 0, nonpos = 0;
-  for (long i = tid; i < m * n; i += stride) bad |= !isfinite(A[i]);
+  if (A)  // a CSR A is checked by its own kernel
+    for (long i = tid; i < m * n; i += stride) bad |= !isfinite(A[i]);
   for (long i = tid; i < m; i += stride) bad |= !isfinite(b[i]) | !isfinite(y[i]);
   for (long i = tid; i < n; i += stride) {
     bad |= !isfinite(c[i]) | !isfinite(x[i]) | !isfinite(s[i]);

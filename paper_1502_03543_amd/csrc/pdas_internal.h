@@ -156,6 +156,32 @@ void launch_wb_cols(hipStream_t st, int m, int n, const double* L, long ld, cons
 void launch_woodbury(hipStream_t st, int m, int n, const double* A, const double* d,
                      const double* Y0, const double* x0, double* dy, DevInfo* info);
 
+// --- sparse A in canonical CSR (kernels_sparse.hip) ------------------------
+constexpr size_t kSparseMaxLds = 160 * 1024;
+size_t sp_syrk_lds_bytes(long m);
+bool sp_fits(long m);               // the normal-matrix kernel's LDS row fits
+hipError_t sp_prepare();            // allows that kernel its dynamic LDS
+// flags: bit 0 bad structure, bit 1 non-finite value (caller zeroes them)
+void launch_sp_check(hipStream_t st, long m, long n, long nnz, const int64_t* rp, const int* ci,
+                     const double* v, int* flags);
+// CSC of a checked CSR: cp (n + 1), ri / cv / src (nnz), map (nnz: CSC
+// position of each CSR entry); cnt, cur: n ints of scratch
+void launch_sp_transpose(hipStream_t st, long m, long n, long nnz, const int64_t* rp,
+                         const int* ci, const double* v, int* cnt, int* cur, int64_t* cp,
+                         int* ri, double* cv, int* src, int* map);
+// out = base + sign * A w
+void launch_sp_gemv_n(hipStream_t st, long m, long nnz, const int64_t* rp, const int* ci,
+                      const double* v, const double* w, const double* base, double* out,
+                      double sign = 1.0);
+// g1 = A^T v1 and, when v2, g2 = A^T v2 (full sums: one chunk)
+void launch_sp_gemv_t(hipStream_t st, long n, long nnz, const int64_t* cp, const int* ri,
+                      const double* cv, const double* v1, const double* v2, double* g1,
+                      double* g2);
+// lower triangle of M = A diag(d) A^T (row-major, ldm)
+void launch_sp_syrk(hipStream_t st, long m, const int64_t* rp, const int* ci, const double* v,
+                    const int64_t* cp, const int* ri, const double* cv, const int* map,
+                    const double* d, double* M, long ldm);
+
 // --- reverse mode (kernels_adjoint.hip) -------------------------------------
 void launch_zero(hipStream_t st, double* p, long count);
 void launch_adj_tbar(hipStream_t st, long m, long n, const double* xb, const double* dx,

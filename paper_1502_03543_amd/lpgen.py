@@ -8,7 +8,7 @@ and x0, s0 > 0 is a valid interior start.
 
 Random streams: numpy's Philox counter-based generator seeded with
 SeedSequence([seed, stream]); stream 0 = A, 1 = x0, 2 = s0, 3 = y0,
-4 = batch shape, 5 = loss weights w.  b and c are computed once here, in
+4 = batch shape, 5 = loss weights w, 6 = the sparsity pattern of a sparse A.  b and c are computed once here, in
 float64, and the same bytes feed both the GPU path and the oracle.
 """
 from __future__ import annotations
@@ -17,7 +17,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-STREAM_A, STREAM_X0, STREAM_S0, STREAM_Y0, STREAM_SHAPE, STREAM_W = range(6)
+STREAM_A, STREAM_X0, STREAM_S0, STREAM_Y0, STREAM_SHAPE, STREAM_W, STREAM_PATTERN = range(7)
 
 
 def _rng(seed: int, stream: int) -> np.random.Generator:
@@ -81,3 +81,43 @@ def gen_batch(count: int, first_seed: int = 0, **shape_kw) -> list[LP]:
 def loss_weights(n: int, seed: int) -> np.ndarray:
     """w ~ N(0,1) for the loss w^T x_K."""
     return _rng(seed, STREAM_W).standard_normal(n)
+
+
+@dataclass
+class SparseLP(LP):
+    """An LP whose A is sparse: CSR arrays beside the dense A (the dense copy
+    serves the oracle; the GPU path takes the CSR arrays)."""
+    row_ptr: np.ndarray = None  # (m + 1,) int64
+    col_idx: np.ndarray = None  # (nnz,) int32, sorted within each row
+    vals: np.ndarray = None     # (nnz,) float64
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+
+def gen_sparse_lp(m: int, n: int, density: float, seed: int = 0) -> SparseLP:
+    """Sparse interior-feasible LP: every row has a nonzero in its own column
+    of a random permutation (so A has full row rank with probability one)
+    plus each other entry independently with probability ``density``; the
+    nonzero values are N(0,1); x0, s0, y0, b and c as in gen_lp."""
+    if not (1 <= m < n) or not (0.0 < density <= 1.0):
+        raise ValueError(f"need 1 <= m < n and 0 < density <= 1, got {m} {n} {density}")
+    pat = _rng(seed, STREAM_PATTERN)
+    mask = pat.random((m, n)) < density
+    perm = pat.permutation(n)[:m]
+    mask[np.arange(m), perm] = True
+    vals_all = _rng(seed, STREAM_A).standard_normal((m, n))
+    A = np.where(mask, vals_all, 0.0)
+    x0 = 0.5 + _rng(seed, STREAM_X0).random(n)
+    s0 = 0.5 + _rng(seed, STREAM_S0).random(n)
+    y0 = _rng(seed, STREAM_Y0).standard_normal(m)
+    b = A @ x0
+    c = A.T @ y0 + s0
+    rows, cols = np.nonzero(mask)  # row-major order: sorted columns within rows
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    return SparseLP(A=np.ascontiguousarray(A), b=b, c=c, x0=x0, y0=y0, s0=s0, seed=seed,
+                    row_ptr=row_ptr, col_idx=cols.astype(np.int32),
+                    vals=np.ascontiguousarray(A[rows, cols]))

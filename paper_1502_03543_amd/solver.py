@@ -164,6 +164,60 @@ class LP:
             pass
 
 
+def _need_csr(row_ptr, col_idx, vals, m):
+    if not all(isinstance(t, torch.Tensor) and t.device.type == "cuda" and t.is_contiguous()
+               for t in (row_ptr, col_idx, vals)):
+        raise TypeError("row_ptr, col_idx and vals must be contiguous CUDA (ROCm) tensors")
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32 or vals.dtype != torch.float64:
+        raise TypeError("row_ptr int64, col_idx int32 and vals float64 are required")
+    if row_ptr.shape != (m + 1,) or col_idx.dim() != 1 or vals.shape != col_idx.shape:
+        raise ValueError("row_ptr must have m + 1 entries and col_idx, vals nnz each")
+    return int(col_idx.shape[0])
+
+
+class CsrLP(LP):
+    """One LP whose A is given in canonical CSR (lp_setup_csr): row_ptr
+    (int64, m + 1), col_idx (int32, nnz, strictly increasing per row), vals
+    (float64, nnz), all borrowed for the handle's lifetime."""
+
+    def __init__(self, row_ptr, col_idx, vals, shape, b, c, x0, y0, s0, **opts):
+        m, n = (int(v) for v in shape)
+        nnz = _need_csr(row_ptr, col_idx, vals, m)
+        for t, shp, nm in ((b, (m,), "b"), (c, (n,), "c"), (x0, (n,), "x0"), (y0, (m,), "y0"),
+                           (s0, (n,), "s0")):
+            _need(t, shp, nm)
+        self.m, self.n, self.nnz = m, n, nnz
+        self.device = b.device
+        self.opts = options(**opts)
+        size = C.c_size_t(0)
+        capi.check(capi.lp_workspace_size_csr(m, n, nnz, C.byref(self.opts), C.byref(size)),
+                   "lp_workspace_size_csr")
+        self._ws, addr = workspace(size.value, b.device)
+        self._A = (row_ptr, col_idx, vals)  # borrowed by the handle
+        h = C.c_void_p()
+        st = capi.lp_setup_csr(C.byref(h), m, n, nnz, _p(row_ptr), _p(col_idx), _p(vals),
+                               _p(b), _p(c), _p(x0), _p(y0), _p(s0), C.byref(self.opts),
+                               C.c_void_p(addr), size.value, _stream())
+        capi.check(st, "lp_setup_csr")
+        self.h = h
+
+
+def normal_matrix_csr(row_ptr, col_idx, vals, shape, d):
+    """Lower triangle of A diag(d) A^T for A in canonical CSR (upper zero)."""
+    m, n = (int(v) for v in shape)
+    nnz = _need_csr(row_ptr, col_idx, vals, m)
+    _need(d, (n,), "d")
+    M = torch.zeros((m, m), dtype=torch.float64, device=d.device)
+    size = C.c_size_t(0)
+    capi.check(capi.lp_csr_workspace_size(m, n, nnz, C.byref(size)), "lp_csr_workspace_size")
+    buf, addr = workspace(size.value, d.device)
+    capi.check(capi.lp_normal_matrix_csr(m, n, nnz, _p(row_ptr), _p(col_idx), _p(vals), _p(d),
+                                         _p(M), m, C.c_void_p(addr), size.value, _stream()),
+               "lp_normal_matrix_csr")
+    torch.cuda.current_stream().synchronize()
+    return M
+
+
 def solve(A, b, c, x0, y0, s0, alpha=0.95, tol=1e-8, max_iter=500, precision="fp64"):
     """Run the Section 3 loop on the GPU.  Returns (x, y, s, info); raises
     RuntimeError (with the status name) on an error status."""

@@ -1,9 +1,10 @@
 """Build the CPU emulation of the library's kernels (test infrastructure only).
 
 The HIP sources are compiled unchanged for the host with tests/emu/hip as the
-runtime, except for three textual substitutions: the inline-asm register
+runtime, except for four textual substitutions: the inline-asm register
 move of the compiler-opaque zero becomes a plain zero, the empty asm that pins
-a value in a vector register disappears, and the workspace carver
+a value in a vector register disappears, a dynamic LDS array becomes the
+emulated launch's LDS block, and the workspace carver
 of the batched solver gains poisoned guard zones between its pools, so that
 AddressSanitizer reports any kernel access that leaves its own pool.
 """
@@ -18,10 +19,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1502_03543_amd", "csrc")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_batch", "api_batch", "kernels_chol", "kernels_syrk", "kernels_trsv"]
+SOURCES = ["kernels_batch", "api_batch", "kernels_chol", "kernels_syrk", "kernels_trsv",
+           "kernels_sparse"]
 
 ASM_ZERO = 'asm volatile("v_mov_b32 %0, 0" : "=v"(z));'
 ASM_PIN = 'asm volatile("" : "+v"(v));'
+DYN_LDS = "extern __shared__ double lds[];"
+DYN_LDS_EMU = "double* lds = reinterpret_cast<double*>(g_emu_dyn_lds);"
 CARVE_OLD = """    off = (off + kAlign - 1) / kAlign * kAlign;
     T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;"""
 CARVE_NEW = """    off = (off + kAlign - 1) / kAlign * kAlign;
@@ -64,6 +68,10 @@ def _build() -> str:
             if ASM_PIN not in text:
                 raise RuntimeError("kernels_chol.hip: register-pin asm not found")
             text = text.replace(ASM_PIN, "(void)v;")
+        if name == "kernels_sparse":
+            if DYN_LDS not in text:
+                raise RuntimeError("kernels_sparse.hip: dynamic LDS declaration not found")
+            text = text.replace(DYN_LDS, DYN_LDS_EMU)
         if name == "api_batch":
             if CARVE_OLD not in text:
                 raise RuntimeError("api_batch.hip: workspace carver not found")

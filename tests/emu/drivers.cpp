@@ -8,6 +8,13 @@
 //   emu trsv <m>                      L z = r and L^T y = z with a fixed
 //                                     lower-triangular L; prints both errors
 //                                     against long-double substitution
+//   emu sparse <m> <n> <pattern>      CSR check, CSC build, A w, A^T v and the
+//                                     sparse normal matrix against long-double
+//                                     references (pattern 0: a dense column,
+//                                     an empty row and column, a row longer
+//                                     than one metadata chunk; 1: uniform,
+//                                     half full), then the check's verdict on
+//                                     broken copies of the CSR
 //   emu batch <in> <out> <max_iter> <tape>
 //                                     batched solve of the LPs in <in>; with a
 //                                     tape, also the reverse sweep
@@ -221,11 +228,162 @@ static int run_batch(const char* in, const char* out, int max_iter, int tape) {
   return 0;
 }
 
+static uint64_t mix64(uint64_t x) {  // splitmix64 finaliser: a fixed hash
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+static double unit(uint64_t a, uint64_t b) { return (mix64(a * 1000003ull + b) >> 11) * 0x1p-53; }
+
+static bool sparse_entry(int pattern, int m, int i, int k) {
+  if (pattern == 1) return unit(i, k) < 0.5;
+  const int longrow = m > 2150 ? 2150 : m / 2;
+  if (i == 7) return false;                                 // an empty row
+  if (k == 0) return true;                                  // a dense column
+  if (k == 1) return false;                                 // an empty column
+  if (i == longrow && k >= 2 && k < 302) return true;       // > one metadata chunk
+  if (k < 42) return unit(i, k) < 0.1;
+  return unit(i, k) < 0.002;
+}
+
+static int sp_flags(long m, long n, const std::vector<int64_t>& rp, const std::vector<int>& ci,
+                    const std::vector<double>& v) {
+  int flags = 0;
+  const long nnz = (long)ci.size();
+  pdas::launch_sp_check(nullptr, m, n, nnz, rp.data(), ci.data(), v.data(), &flags);
+  return flags;
+}
+
+static int run_sparse(int m, int n, int pattern) {
+  std::vector<int64_t> rp(m + 1, 0);
+  std::vector<int> ci;
+  std::vector<double> v;
+  for (int i = 0; i < m; ++i) {
+    for (int k = 0; k < n; ++k)
+      if (sparse_entry(pattern, m, i, k)) {
+        ci.push_back(k);
+        v.push_back(2.0 * unit(i + 77, k) - 1.0);
+      }
+    rp[i + 1] = (int64_t)ci.size();
+  }
+  const long nnz = (long)ci.size();
+  const int flags = sp_flags(m, n, rp, ci, v);
+  std::vector<int> cnt(n), cur(n), ri(nnz + 1), src(nnz + 1), map(nnz + 1);
+  std::vector<int64_t> cp(n + 1, -1);
+  std::vector<double> cv(nnz + 1);
+  pdas::launch_sp_transpose(nullptr, m, n, nnz, rp.data(), ci.data(), v.data(), cnt.data(),
+                            cur.data(), cp.data(), ri.data(), cv.data(), src.data(), map.data());
+  // CSC: column counts, rows increasing, values and the CSR -> CSC map
+  int csc_bad = 0;
+  std::vector<int64_t> colcount(n + 1, 0);
+  for (long e = 0; e < nnz; ++e) colcount[ci[e] + 1]++;
+  for (int k = 0; k < n; ++k) colcount[k + 1] += colcount[k];
+  for (int k = 0; k <= n; ++k) csc_bad += cp[k] != colcount[k];
+  for (int k = 0; k < n && !csc_bad; ++k)
+    for (int64_t p = cp[k] + 1; p < cp[k + 1]; ++p) csc_bad += ri[p] <= ri[p - 1];
+  for (int i = 0; i < m; ++i)
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int p = map[e];
+      csc_bad += !(p >= cp[ci[e]] && p < cp[ci[e] + 1]) || ri[p] != i || cv[p] != v[e];
+    }
+  // products
+  std::vector<double> w(n), d(n), base(m), u1(m), u2(m), out(m, NAN), g1(n, NAN), g2(n, NAN);
+  for (int k = 0; k < n; ++k) {
+    w[k] = std::sin(0.37 * k + 0.1);
+    d[k] = 0.25 + unit(k, 991);
+  }
+  for (int i = 0; i < m; ++i) {
+    base[i] = std::cos(0.11 * i);
+    u1[i] = std::sin(0.23 * i + 0.7);
+    u2[i] = std::cos(0.19 * i + 0.2);
+  }
+  pdas::launch_sp_gemv_n(nullptr, m, nnz, rp.data(), ci.data(), v.data(), w.data(), base.data(),
+                         out.data(), -1.0);
+  pdas::launch_sp_gemv_t(nullptr, n, nnz, cp.data(), ri.data(), cv.data(), u1.data(), u2.data(),
+                         g1.data(), g2.data());
+  double en = 0, sn = 0, et = 0, st = 0;
+  for (int i = 0; i < m; ++i) {
+    long double r = 0, a = 0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      r += (long double)v[e] * w[ci[e]];
+      a += std::fabs(v[e] * w[ci[e]]);
+    }
+    en = worse(en, std::fabs((double)(out[i] - (base[i] - r))));
+    sn = std::fmax(sn, (double)a + std::fabs(base[i]));
+  }
+  std::vector<long double> t1(n, 0), t2(n, 0), ta(n, 0);
+  for (int i = 0; i < m; ++i)
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      t1[ci[e]] += (long double)v[e] * u1[i];
+      t2[ci[e]] += (long double)v[e] * u2[i];
+      ta[ci[e]] += std::fabs(v[e]);
+    }
+  for (int k = 0; k < n; ++k) {
+    et = worse(et, std::fabs((double)(g1[k] - t1[k])));
+    et = worse(et, std::fabs((double)(g2[k] - t2[k])));
+    st = std::fmax(st, (double)ta[k]);
+  }
+  // normal matrix: reference summed over the CSC in long double
+  const long ldm = m + 3;
+  std::vector<double> M((size_t)m * ldm, NAN);
+  pdas::launch_sp_syrk(nullptr, m, rp.data(), ci.data(), v.data(), cp.data(), ri.data(),
+                       cv.data(), map.data(), d.data(), M.data(), ldm);
+  double em = 0, sm = 0;
+  int upper_touched = 0;
+  std::vector<long double> acc(m);
+  for (int i = 0; i < m; ++i) {
+    std::fill(acc.begin(), acc.end(), 0.0L);
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int k = ci[e];
+      for (int64_t p = colcount[k]; p < colcount[k + 1]; ++p)
+        if (ri[p] <= i) acc[ri[p]] += (long double)d[k] * v[e] * cv[p];
+    }
+    for (int j = 0; j <= i; ++j) {
+      em = worse(em, std::fabs((double)(M[(size_t)i * ldm + j] - acc[j])));
+      sm = std::fmax(sm, std::fabs((double)acc[j]));
+    }
+    for (int j = i + 1; j < ldm; ++j) upper_touched += !std::isnan(M[(size_t)i * ldm + j]);
+  }
+  // the check on broken copies: unsorted row, column out of range, NaN,
+  // row_ptr[m] != nnz, a decreasing row_ptr
+  int longrow = 0;
+  for (int i = 0; i < m; ++i)
+    if (rp[i + 1] - rp[i] > rp[longrow + 1] - rp[longrow]) longrow = i;
+  auto ci2 = ci;
+  std::swap(ci2[rp[longrow]], ci2[rp[longrow] + 1]);
+  const int f_unsorted = sp_flags(m, n, rp, ci2, v);
+  ci2 = ci;
+  ci2[nnz - 1] = n;
+  const int f_range = sp_flags(m, n, rp, ci2, v);
+  auto v2 = v;
+  v2[nnz / 2] = NAN;
+  const int f_nan = sp_flags(m, n, rp, ci, v2);
+  auto rp2 = rp;
+  rp2[m] = nnz - 1;
+  std::vector<int> ci3(ci.begin(), ci.end() - 1);
+  std::vector<double> v3(v.begin(), v.end() - 1);
+  rp2[m] = nnz;  // row_ptr says nnz, the arrays hold nnz - 1: rp[m] != nnz of the call
+  const int f_count = sp_flags(m, n, rp2, ci3, v3);
+  rp2 = rp;
+  rp2[longrow + 1] = rp[longrow] - 1;
+  const int f_order = sp_flags(m, n, rp2, ci, v);
+  printf("{\"m\": %d, \"n\": %d, \"nnz\": %ld, \"flags\": %d, \"csc_bad\": %d, "
+         "\"gemv_n_rel_err\": %.3e, \"gemv_t_rel_err\": %.3e, \"syrk_rel_err\": %.3e, "
+         "\"upper_touched\": %d, \"f_unsorted\": %d, \"f_range\": %d, \"f_nan\": %d, "
+         "\"f_count\": %d, \"f_order\": %d}\n",
+         m, n, nnz, flags, csc_bad, en / sn, et / st, em / sm, upper_touched, f_unsorted,
+         f_range, f_nan, f_count, f_order);
+  return 0;
+}
+
 int main(int argc, char** argv) {
   if (argc >= 3 && !strcmp(argv[1], "chol")) return run_chol(atoi(argv[2]));
   if (argc >= 6 && !strcmp(argv[1], "syrk"))
     return run_syrk(atoi(argv[2]), atoi(argv[3]), atoi(argv[4]), atoi(argv[5]));
   if (argc >= 3 && !strcmp(argv[1], "trsv")) return run_trsv(atoi(argv[2]));
+  if (argc >= 5 && !strcmp(argv[1], "sparse"))
+    return run_sparse(atoi(argv[2]), atoi(argv[3]), atoi(argv[4]));
   if (argc >= 6 && !strcmp(argv[1], "batch"))
     return run_batch(argv[2], argv[3], atoi(argv[4]), atoi(argv[5]));
   fprintf(stderr, "usage: emu chol <m> | emu batch <in> <out> <max_iter> <tape>\n");

@@ -16,6 +16,7 @@ EmuBarrier g_wave_bar[kEmuWaves];
 uint64_t g_wave_buf[kEmuWaves][64];
 uint64_t g_wave_buf2[kEmuWaves][64];
 long g_barrier_count = 0;
+char* g_emu_dyn_lds = nullptr;
 long g_progress = 0;
 
 extern "C" void emu_switch(void** save_sp, void* load_sp);

@@ -217,17 +217,29 @@ using std::min;
 using std::max;
 
 void emu_run_block(int nt, std::function<void()> body);
+// dynamic LDS ("extern __shared__" arrays): a heap block of exactly the
+// launch's size, refilled with NaN bytes before every workgroup (LDS holds
+// no data from an earlier workgroup), so reads beyond it are reported and
+// reads before a write show up as NaN
+extern char* g_emu_dyn_lds;
 template <typename... KA, typename... A>
-inline void emu_launch(void (*k)(KA...), dim3 grid, dim3 block, A... args) {
+inline void emu_launch(void (*k)(KA...), dim3 grid, dim3 block, size_t shm, A... args) {
   blockDim = block;
   gridDim = grid;
+  char* dyn = shm ? new char[shm] : nullptr;
+  g_emu_dyn_lds = dyn;
   for (unsigned by = 0; by < grid.y; ++by)
     for (unsigned bx = 0; bx < grid.x; ++bx) {
       blockIdx = dim3(bx, by, 0);
+      if (dyn) std::memset(dyn, 0xff, shm);
       emu_run_block(block.x, [=] { k(args...); });
     }
+  delete[] dyn;
+  g_emu_dyn_lds = nullptr;
 }
-#define hipLaunchKernelGGL(k, grid, block, shm, st, ...) emu_launch(k, dim3(grid), dim3(block), __VA_ARGS__)
+#define hipLaunchKernelGGL(k, grid, block, shm, st, ...) emu_launch(k, dim3(grid), dim3(block), (size_t)(shm), __VA_ARGS__)
+enum { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
+inline hipError_t hipFuncSetAttribute(const void*, int, int) { return hipSuccess; }
 
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr) { return hipSuccess; }

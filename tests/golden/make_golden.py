@@ -19,13 +19,20 @@ runs take minutes, so that the GPU tests can compare against them directly:
                                1e-8: per-LP status, K and objectives
   lp2048x8192_seed0_pc.json    the m=2048 instance under the predictor-corrector
                                variant: status, K, objectives, per-iteration log
+  lp2048x8192_d01_seed0_csr.json
+                               sparse instance (density 1%, seed 0, every row
+                               with one guaranteed entry): the same record
+                               as lp2048x8192_seed0.json, solved by the
+                               oracle on its dense form
+  lp2048x8192_d01_seed0_csr_dy0.npy
+                               its first direction dy (float64, m)
   fd_lp256x1024_K30.json       64-LP reverse-mode workload (m=256, n=1024,
                                K=30, alpha 0.9, loss w^T x_K): central
                                differences of the loss along seeded directions
                                of A, b and c, in the long-double oracle, at
                                h = 1e-6 and h/2, for a sample of LPs
 
-Usage: python tests/golden/make_golden.py [c1] [c2] [c2pc] [c3] [c4] [c5]
+Usage: python tests/golden/make_golden.py [c1] [c2] [c2pc] [c2sp] [c3] [c4] [c5]
 (no argument: all).  The m=2048 solve takes a few minutes on 8 cores, the
 m=8192 direction several more.
 """
@@ -121,6 +128,18 @@ def c2pc():
     _dump("lp2048x8192_seed0_pc.json", rec)
 
 
+def c2sp():
+    """The sparse m=2048 instance (1% density) solved by the oracle on the
+    densified matrix."""
+    lp = lpgen.gen_sparse_lp(2048, 8192, 0.01, 0)
+    it, first = _first_direction(lp, 0.95)
+    np.save(os.path.join(HERE, "lp2048x8192_d01_seed0_csr_dy0.npy"), it.dy)
+    del it
+    rec = _solve_record(lp, 0.95, 1e-8, 200)
+    rec.update(first_direction=first, density=0.01, nnz=lp.nnz)
+    _dump("lp2048x8192_d01_seed0_csr.json", rec)
+
+
 def c3():
     t0 = time.time()
     lp = lpgen.gen_lp(8192, 32768, 0)
@@ -169,7 +188,7 @@ def c5():
 
 
 if __name__ == "__main__":
-    todo = sys.argv[1:] or ["c1", "c2", "c2pc", "c4", "c5", "c3"]
+    todo = sys.argv[1:] or ["c1", "c2", "c2pc", "c2sp", "c4", "c5", "c3"]
     for name in todo:
         t0 = time.time()
         globals()[name]()

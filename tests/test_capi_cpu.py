@@ -94,3 +94,41 @@ def test_solver_validation():
         setattr(o, field, old)
     o.solver = 2
     assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+
+
+def test_csr_validation():
+    """lp_setup_csr's workspace rules: FP64 Cholesky without a tape (either
+    method), m <= LP_CSR_MAX_M, 0 <= nnz <= INT32_MAX; the sparse workspace
+    holds the CSC (index, value and map arrays) but no split-K scratch."""
+    o = capi.lp_options()
+    capi.lp_options_default(C.byref(o))
+    sz = C.c_size_t(0)
+    dense = C.c_size_t(0)
+    assert capi.lp_workspace_size_csr(2048, 8192, 170000, C.byref(o), C.byref(sz)) == capi.LP_OK
+    assert capi.lp_workspace_size(2048, 8192, C.byref(o), C.byref(dense)) == capi.LP_OK
+    assert sz.value % 256 == 0 and sz.value >= 2048 * 2048 * 8 + 170000 * 20
+    assert capi.lp_workspace_size_csr(64, 256, 0, C.byref(o), C.byref(sz)) == capi.LP_OK
+    assert capi.lp_workspace_size_csr(16384, 20000, 10, C.byref(o), C.byref(sz)) == capi.LP_OK
+    assert capi.lp_workspace_size_csr(16385, 20000, 10, C.byref(o),
+                                      C.byref(sz)) == capi.LP_ERR_SHAPE
+    assert capi.lp_workspace_size_csr(64, 256, -1, C.byref(o), C.byref(sz)) == capi.LP_ERR_SHAPE
+    assert capi.lp_workspace_size_csr(64, 256, 2 ** 31, C.byref(o),
+                                      C.byref(sz)) == capi.LP_ERR_SHAPE
+    assert capi.lp_workspace_size_csr(64, 64, 10, C.byref(o), C.byref(sz)) == capi.LP_ERR_SHAPE
+    o.method = capi.LP_METHOD_PC
+    assert capi.lp_workspace_size_csr(64, 256, 100, C.byref(o), C.byref(sz)) == capi.LP_OK
+    o.method = capi.LP_METHOD_AFFINE
+    for field, value in (("precision", capi.LP_PREC_MIXED), ("solver", capi.LP_SOLVER_WOODBURY),
+                         ("tape_capacity", 2)):
+        old = getattr(o, field)
+        setattr(o, field, value)
+        assert capi.lp_workspace_size_csr(64, 256, 100, C.byref(o),
+                                          C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+        setattr(o, field, old)
+    assert capi.lp_csr_workspace_size(64, 256, 100, C.byref(sz)) == capi.LP_OK
+    assert capi.lp_csr_workspace_size(16385, 256, 100, C.byref(sz)) == capi.LP_ERR_SHAPE
+    h = C.c_void_p()
+    dummy = C.c_void_p(256)
+    st = capi.lp_setup_csr(C.byref(h), 8, 16, 10, dummy, dummy, dummy, dummy, dummy, dummy,
+                           dummy, dummy, C.byref(o), None, 0, None)
+    assert st == capi.LP_ERR_WORKSPACE and not h.value
