@@ -124,6 +124,10 @@ def batch_variant(lpgen, solver, capi, torch, sample: int = 32) -> dict:
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     names = [capi.status_string(int(v)) for v in res["status"]]
+    launch = {"batch_tile": int(bt.opts.batch_tile) or 64,
+              "batch_graph_iters": int(bt.opts.batch_graph_iters) or 4,
+              "source": "autotune cache" if solver.tuned_batch_launch(bt.m, bt.n)
+              else "library default"}
     bt.close()
     dev = torch.device("cuda:0")
     hs = []
@@ -144,6 +148,7 @@ def batch_variant(lpgen, solver, capi, torch, sample: int = 32) -> dict:
                     "alpha 0.95, to gap 1e-8",
         "batched_lps_per_s": len(lps) / tb,
         "batched_ms": tb * 1e3,
+        "launch": launch,
         "fp64_lp_by_lp_lps_per_s": sample / ts,
         "lp_by_lp_sample": f"single-LP solver on LPs 0..{sample - 1}, one after another",
         "speedup_vs_lp_by_lp": (len(lps) / tb) / (sample / ts),

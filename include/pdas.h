@@ -128,7 +128,15 @@ typedef struct lp_options {
   int32_t syrk32_splits;   /* FP32 normal-matrix split (MIXED): 0 or 1..64      */
   int32_t method;          /* lp_method (default LP_METHOD_AFFINE)               */
   int32_t solver;          /* lp_solver (default LP_SOLVER_CHOLESKY)             */
+  int32_t batch_tile;      /* lp_batch_*: normal-matrix and trailing-update tile
+                              edge, 0 (library's choice: 64), 32 or 64; see
+                              paper_1502_03543_amd/autotune.py.  Ignored by the
+                              single-LP calls (which accept only these values) */
+  int32_t batch_graph_iters; /* lp_batch_solve: iterations captured per
+                              hipGraph and replayed between host checks, 0
+                              (library's choice: 4) or 1..16                    */
   int32_t reserved;        /* must be 0                                          */
+  int32_t reserved2;       /* must be 0                                          */
 } lp_options;
 
 /* Fill *opt with the defaults: alpha 0.95, FP64, no tape, switch gap 1e-6,

@@ -56,7 +56,10 @@ class lp_options(C.Structure):
         ("syrk32_splits", C.c_int32),
         ("method", C.c_int32),
         ("solver", C.c_int32),
+        ("batch_tile", C.c_int32),
+        ("batch_graph_iters", C.c_int32),
         ("reserved", C.c_int32),
+        ("reserved2", C.c_int32),
     ]
 
 

@@ -18,7 +18,7 @@ using namespace pdas;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kItersPerGraph = 4;
+constexpr int kItersPerGraph = 4;  // default of lp_options.batch_graph_iters
 
 struct Carver {
   char* base;
@@ -114,6 +114,7 @@ __global__ void k_batch_tape_row(int count, const BatchLP* lps, const BatchState
 
 struct lp_batch {
   int count = 0;
+  int graph_iters = kItersPerGraph;
   lp_options opt{};
   hipStream_t st = nullptr;
   std::vector<BatchLP> lps_h;
@@ -246,6 +247,9 @@ lp_status lp_batch_workspace_size(int32_t count, const int64_t* m, const int64_t
   if (opt) o = *opt;
   if (!(o.alpha > 0.0 && o.alpha < 1.0) || o.tape_capacity < 0) return LP_ERR_INVALID_ARG;
   if (o.precision != LP_PREC_FP64 || o.method != LP_METHOD_AFFINE) return LP_ERR_INVALID_ARG;
+  if (o.solver != LP_SOLVER_CHOLESKY || o.reserved != 0 || o.reserved2 != 0) return LP_ERR_INVALID_ARG;
+  if (o.batch_tile != 0 && o.batch_tile != 32 && o.batch_tile != 64) return LP_ERR_INVALID_ARG;
+  if (o.batch_graph_iters < 0 || o.batch_graph_iters > 16) return LP_ERR_INVALID_ARG;
   lp_batch h;
   h.count = count;
   h.opt = o;
@@ -298,6 +302,8 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
   a.A = A_packed;
   a.lps = h->lps;
   a.state = h->state;
+  a.tile = h->opt.batch_tile ? h->opt.batch_tile : 64;
+  h->graph_iters = h->opt.batch_graph_iters ? h->opt.batch_graph_iters : kItersPerGraph;
   a.alpha = h->opt.alpha;
   for (int i = 0; i < count; ++i) {
     h->max_m = std::max(h->max_m, (int)m[i]);
@@ -363,7 +369,7 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
   BatchArgs a = h->args;
   a.tol = gap_tol;
   a.max_iter = max_iter;
-  // Capture kItersPerGraph iterations into one graph and replay it.  The
+  // Capture graph_iters iterations into one graph and replay it.  The
   // legacy default stream cannot be captured; there the same launches are
   // issued directly.
   hipGraph_t graph = nullptr;
@@ -372,18 +378,18 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
   if (s != nullptr) {
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      for (int k = 0; k < kItersPerGraph; ++k) launch_batch_step(s, a, h->max_m, -1, nullptr);
+      for (int k = 0; k < h->graph_iters; ++k) launch_batch_step(s, a, h->max_m, -1, nullptr);
       e = hipStreamEndCapture(s, &graph);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   }
   int launches = 0;
-  const int max_launches = max_iter / kItersPerGraph + 2;
+  const int max_launches = max_iter / h->graph_iters + 2;
   while (e == hipSuccess) {
     if (exec) {
       e = hipGraphLaunch(exec, s);
     } else {
-      for (int k = 0; k < kItersPerGraph; ++k) launch_batch_step(s, a, h->max_m, -1, nullptr);
+      for (int k = 0; k < h->graph_iters; ++k) launch_batch_step(s, a, h->max_m, -1, nullptr);
       e = hipGetLastError();
     }
     int active = 0;

@@ -751,10 +751,10 @@ void launch_batch_step(hipStream_t st, const BatchArgs& a, int max_m, int k,
   if (k < 0) hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, st, a.active);
   hipLaunchKernelGGL(k_bbegin, dim3(count), dim3(256), 0, st, a, k);
   hipLaunchKernelGGL(k_brhs, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a);
-  launch_bsyrk_normal(st, count, max_m, a.lps, a.go, a.A, a.d, a.M);
+  launch_bsyrk_normal(st, count, max_m, a.tile, a.lps, a.go, a.A, a.d, a.M);
   for (int p = 0; p < max_m; p += BT) {
     launch_bpotrf_panel(st, count, max_m, a.lps, a.go, a.M, a.diag, p, a.fail, a.minp);
-    launch_bsyrk_trailing(st, count, max_m, a.lps, a.go, a.M, p);
+    launch_bsyrk_trailing(st, count, max_m, a.tile, a.lps, a.go, a.M, p);
   }
   launch_bdiag_to_m(st, count, max_m, a.lps, a.go, a.M, a.diag);
   hipLaunchKernelGGL(k_btrsv, dim3(count), dim3(256), 0, st, a, k, err);

@@ -193,8 +193,11 @@ __global__ __launch_bounds__(256) void k_syrk_reduce_f32(int mm, float* __restri
 constexpr int kKC128 = 32;  // K per stage of the 128 x 128 tile kernel
 constexpr int kKC64 = 32;   // and of the 64 x 64 one
 
-// Batched normal matrices: LP = blockIdx.y, lower 64-tile blockIdx.x of
+// Batched normal matrices: LP = blockIdx.y, lower BM-tile blockIdx.x of
 // M_i = A_i diag(d_i) A_i^T (rows of A_i need not be 16-byte aligned).
+// BM = 64 (2 x 2 wavefronts of 32 x 32) or 32 (of 16 x 16): the smaller
+// tile wastes less on small LPs and gives more workgroups per LP.
+template <int BM>
 __global__ __launch_bounds__(256) void k_bsyrk_normal(const BatchLP* __restrict__ lps,
                                                        const int* __restrict__ go,
                                                        const double* __restrict__ A,
@@ -203,16 +206,18 @@ __global__ __launch_bounds__(256) void k_bsyrk_normal(const BatchLP* __restrict_
   const int lp = blockIdx.y;
   if (!go[lp]) return;
   const BatchLP P = lps[lp];
-  const int nt = (P.m + 63) / 64, ntiles = nt * (nt + 1) / 2;
+  const int nt = (P.m + BM - 1) / BM, ntiles = nt * (nt + 1) / 2;
   const int t = blockIdx.x;
   if (t >= ntiles) return;
-  __shared__ double2 lds2[syrk_tile_lds2<8, 32>()];
-  syrk_f64_tile<8, 2, 32, true, false>(P.m, P.n, A + P.a_off, P.n, d + P.vn, Mpool + P.M_off,
-                                       P.ldm, 0, t, ntiles, 0, 1, P.n, nullptr, lds2);
+  __shared__ double2 lds2[syrk_tile_lds2<BM / 8, 32>()];
+  syrk_f64_tile<BM / 8, BM / 32, 32, true, false>(P.m, P.n, A + P.a_off, P.n, d + P.vn,
+                                                  Mpool + P.M_off, P.ldm, 0, t, ntiles, 0, 1, P.n,
+                                                  nullptr, lds2);
 }
 
 // Batched Cholesky trailing update after the panel at column p:
-// M22 -= L21 L21^T on the lower 64-tiles of each LP that has rows below p + 64.
+// M22 -= L21 L21^T on the lower BM-tiles of each LP that has rows below p + 64.
+template <int BM>
 __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restrict__ lps,
                                                          const int* __restrict__ go,
                                                          double* __restrict__ Mpool, int p) {
@@ -221,13 +226,13 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restric
   const BatchLP P = lps[lp];
   const int mm = P.m - p - 64;
   if (mm <= 0) return;
-  const int nt = (mm + 63) / 64, ntiles = nt * (nt + 1) / 2;
+  const int nt = (mm + BM - 1) / BM, ntiles = nt * (nt + 1) / 2;
   const int t = blockIdx.x;
   if (t >= ntiles) return;
   double* X = Mpool + P.M_off + (long)(p + 64) * P.ldm + p;
-  __shared__ double2 lds2[syrk_tile_lds2<8, 32>()];
-  syrk_f64_tile<8, 2, 32, false, true>(mm, 64, X, P.ldm, nullptr, X + 64, P.ldm, 1, t, ntiles, 0,
-                                       1, 64, nullptr, lds2);
+  __shared__ double2 lds2[syrk_tile_lds2<BM / 8, 32>()];
+  syrk_f64_tile<BM / 8, BM / 32, 32, false, true>(mm, 64, X, P.ldm, nullptr, X + 64, P.ldm, 1, t,
+                                                  ntiles, 0, 1, 64, nullptr, lds2);
 }
 
 // ---------------------------------------------------------------------------
@@ -632,20 +637,28 @@ bool launch_syrk_f32(hipStream_t st, int mm, int K, const float* X, long ldx, co
   return true;
 }
 
-void launch_bsyrk_normal(hipStream_t st, int count, int max_m, const BatchLP* lps, const int* go,
-                         const double* A, const double* d, double* Mpool) {
-  const int nt = cdiv(max_m, 64);
-  hipLaunchKernelGGL(k_bsyrk_normal, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st, lps, go, A,
-                     d, Mpool);
+void launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
+                         const int* go, const double* A, const double* d, double* Mpool) {
+  const int nt = cdiv(max_m, tile);
+  if (tile == 32)
+    hipLaunchKernelGGL(k_bsyrk_normal<32>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st, lps,
+                       go, A, d, Mpool);
+  else
+    hipLaunchKernelGGL(k_bsyrk_normal<64>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st, lps,
+                       go, A, d, Mpool);
 }
 
-void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, const BatchLP* lps,
+void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                            const int* go, double* Mpool, int p) {
   const int mm = max_m - p - 64;
   if (mm <= 0) return;
-  const int nt = cdiv(mm, 64);
-  hipLaunchKernelGGL(k_bsyrk_trailing, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st, lps, go,
-                     Mpool, p);
+  const int nt = cdiv(mm, tile);
+  if (tile == 32)
+    hipLaunchKernelGGL(k_bsyrk_trailing<32>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
+                       lps, go, Mpool, p);
+  else
+    hipLaunchKernelGGL(k_bsyrk_trailing<64>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
+                       lps, go, Mpool, p);
 }
 
 }  // namespace pdas

@@ -241,6 +241,7 @@ struct BatchArgs {
   unsigned long long* minp;  // per LP: smallest pivot (bit pattern of a positive double)
   double* psi;          // per LP: psi of the current direction
   long long* arg;       // per LP: its first maximiser (x block j, s block n + j)
+  int tile;             // edge of the normal-matrix and trailing-update tiles (32, 64)
   int nslice;           // 256-column slices of the widest LP
   double* dpv;          // per LP and slice: the slice's ratio-test maximum,
   long long* dpi;       //   its first maximiser
@@ -272,9 +273,10 @@ void launch_batch_setup(hipStream_t st, int count, const BatchLP* lps, BatchStat
                         const double* Ap, const double* c, const double* x, const double* y,
                         const double* s, double* rd);
 // batched building blocks (kernels_syrk.hip, kernels_chol.hip)
-void launch_bsyrk_normal(hipStream_t st, int count, int max_m, const BatchLP* lps, const int* go,
-                         const double* A, const double* d, double* Mpool);
-void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, const BatchLP* lps,
+// tile: 32 or 64 (the edge of the lower tiles)
+void launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
+                         const int* go, const double* A, const double* d, double* Mpool);
+void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                            const int* go, double* Mpool, int p);
 void launch_bpotrf_panel(hipStream_t st, int count, int max_m, const BatchLP* lps, const int* go,
                          double* Mpool, double* diagpool, int p, int* fail,

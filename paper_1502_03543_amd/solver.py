@@ -43,7 +43,8 @@ def workspace(nbytes: int, device) -> tuple[torch.Tensor, int]:
 
 def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6,
             refine_tol=2.0 ** -46, refine_max=5, profile=False, syrk_tile=0, syrk_splits=0,
-            syrk32_splits=0, method="affine", solver="cholesky") -> capi.lp_options:
+            syrk32_splits=0, method="affine", solver="cholesky", batch_tile=0,
+            batch_graph_iters=0) -> capi.lp_options:
     o = capi.lp_options()
     capi.lp_options_default(C.byref(o))
     o.alpha = float(alpha)
@@ -58,6 +59,8 @@ def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6
     o.syrk32_splits = int(syrk32_splits)
     o.method = _METHOD[method]
     o.solver = _SOLVER[solver]
+    o.batch_tile = int(batch_tile)
+    o.batch_graph_iters = int(batch_graph_iters)
     return o
 
 
@@ -75,6 +78,15 @@ def tuned_launch(precision: str, m: int, n: int) -> dict:
         if e32:
             out["syrk32_splits"] = e32["choice"]["syrk32_splits"]
     return out
+
+
+def tuned_batch_launch(m, n) -> dict:
+    """Batched launch choices (tile, iterations per graph) measured by the
+    autotuner for a batch of this shape signature (empty when none)."""
+    from . import autotune
+
+    e = autotune.lookup_batch(m, n)
+    return dict(e["choice"]) if e else {}
 
 
 class LP:
@@ -286,7 +298,8 @@ class Batch:
     x0, y0, s0; they are packed on the host, uploaded once, and solved by the
     batched kernel.  FP64."""
 
-    def __init__(self, problems, alpha=0.95, tape_capacity=0, device="cuda"):
+    def __init__(self, problems, alpha=0.95, tape_capacity=0, device="cuda", batch_tile=None,
+                 batch_graph_iters=None):
         import numpy as np
 
         self.count = len(problems)
@@ -306,7 +319,12 @@ class Batch:
         self.y0 = torch.from_numpy(cat("y0")).to(dev)
         self.s0 = torch.from_numpy(cat("s0")).to(dev)
         self.device = dev
-        self.opts = options(alpha=alpha, tape_capacity=tape_capacity)
+        if batch_tile is None and batch_graph_iters is None:
+            tuned = tuned_batch_launch(self.m, self.n)
+            batch_tile = tuned.get("batch_tile", 0)
+            batch_graph_iters = tuned.get("batch_graph_iters", 0)
+        self.opts = options(alpha=alpha, tape_capacity=tape_capacity,
+                            batch_tile=batch_tile or 0, batch_graph_iters=batch_graph_iters or 0)
         I64 = C.c_int64 * self.count
         self._m, self._n = I64(*self.m), I64(*self.n)
         self._aoff, self._vom, self._von = I64(*self.a_off), I64(*self.v_off_m), I64(*self.v_off_n)

@@ -58,8 +58,15 @@ struct EmuBarrier {
   int count = 0, target = 0;
   long gen = 0;
   const char* name = "";
-  void init(int n, const char* nm) { target = n; count = 0; name = nm; }
+  // workgroup barriers: the source line the first thread of the current
+  // generation waited at; every other thread must wait at the same line
+  // (on the hardware a wavefront whose lanes reach two different barrier
+  // instructions executes both, and the workgroup's count goes wrong)
+  const char* site_file = nullptr;
+  int site_line = 0;
+  void init(int n, const char* nm) { target = n; count = 0; name = nm; site_file = nullptr; }
   void wait();
+  void wait_at(const char* file, int line);
 };
 extern EmuBarrier g_block_bar;
 constexpr int kEmuWaves = 16;  // up to 1024 threads per workgroup
@@ -80,10 +87,22 @@ inline void EmuBarrier::wait() {
   while (gen == g) emu_yield();
 }
 
-inline void __syncthreads() {
-  if (threadIdx.x == 0) ++g_barrier_count;
-  g_block_bar.wait();
+inline void EmuBarrier::wait_at(const char* file, int line) {
+  if (count == 0) {
+    site_file = file;
+    site_line = line;
+  } else if (line != site_line || std::strcmp(file, site_file) != 0) {
+    fprintf(stderr, "EMU BARRIER SITE MISMATCH block %u thread %u: %s:%d while the generation "
+            "waits at %s:%d\n", blockIdx.x, threadIdx.x, file, line, site_file, site_line);
+    std::abort();
+  }
+  wait();
 }
+inline void emu_syncthreads(const char* file, int line) {
+  if (threadIdx.x == 0) ++g_barrier_count;
+  g_block_bar.wait_at(file, line);
+}
+#define __syncthreads() emu_syncthreads(__FILE__, __LINE__)
 inline void __threadfence() {}
 // a wavefront runs in lock-step on the hardware; the emulation makes the
 // points the kernels mark explicit synchronisation points of the wavefront

@@ -32,11 +32,14 @@ def _oracle_check(lp, status, iters, x, y, s, strict_iters=True):
         assert x @ s < 1e-8 and np.all(x > 0) and np.all(s > 0)
 
 
-def test_batch_small_matches_oracle(torch_dev):
+@pytest.mark.parametrize("tile,giters", [(0, 0), (32, 1), (64, 8), (32, 3)])
+def test_batch_small_matches_oracle(torch_dev, tile, giters):
+    """Every launch choice the autotuner may pick (tile edge 32 or 64,
+    iterations per captured graph) against the oracle, LP by LP."""
     from paper_1502_03543_amd import solver
     lps = lpgen.gen_batch(24, first_seed=100)
-    print("shapes:", [lp.A.shape for lp in lps], flush=True)
-    bt = solver.Batch(lps, alpha=0.95)
+    print("shapes:", [lp.A.shape for lp in lps], f"tile={tile} graph_iters={giters}", flush=True)
+    bt = solver.Batch(lps, alpha=0.95, batch_tile=tile, batch_graph_iters=giters)
     print("batch set up, solving", flush=True)
     res = bt.solve(1e-8, 200)
     print("solved:", list(res["iters"]), flush=True)

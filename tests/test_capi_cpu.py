@@ -132,3 +132,26 @@ def test_csr_validation():
     st = capi.lp_setup_csr(C.byref(h), 8, 16, 10, dummy, dummy, dummy, dummy, dummy, dummy,
                            dummy, dummy, C.byref(o), None, 0, None)
     assert st == capi.LP_ERR_WORKSPACE and not h.value
+
+
+def test_batch_launch_options():
+    """lp_options.batch_tile (0, 32, 64) and batch_graph_iters (0..16) are
+    validated by the single-LP and the batched workspace calls alike."""
+    o = capi.lp_options()
+    capi.lp_options_default(C.byref(o))
+    assert o.batch_tile == 0 and o.batch_graph_iters == 0 and o.reserved2 == 0
+    sz = C.c_size_t(0)
+    m = (C.c_int64 * 2)(16, 20)
+    n = (C.c_int64 * 2)(40, 60)
+    for tile, g, ok in ((32, 1, True), (64, 16, True), (0, 0, True), (16, 0, False),
+                        (128, 0, False), (32, 17, False), (32, -1, False)):
+        o.batch_tile, o.batch_graph_iters = tile, g
+        want = capi.LP_OK if ok else capi.LP_ERR_INVALID_ARG
+        assert capi.lp_batch_workspace_size(2, m, n, C.byref(o), C.byref(sz)) == want, (tile, g)
+        assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == want, (tile, g)
+    o.batch_tile, o.batch_graph_iters = 0, 0
+    o.reserved2 = 1
+    assert capi.lp_workspace_size(64, 256, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG
+    o.reserved2 = 0
+    o.solver = capi.LP_SOLVER_WOODBURY
+    assert capi.lp_batch_workspace_size(2, m, n, C.byref(o), C.byref(sz)) == capi.LP_ERR_INVALID_ARG

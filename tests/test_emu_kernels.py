@@ -103,10 +103,11 @@ def _lps():
     return lps + [bad]
 
 
-def test_emulated_batch_matches_oracle(emu, tmp_path):
+@pytest.mark.parametrize("tile", [0, 32])
+def test_emulated_batch_matches_oracle(emu, tmp_path, tile):
     lps = _lps()
     _write(tmp_path / "in.bin", lps)
-    _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0)
+    _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0, tile)
     raw = (tmp_path / "out.bin").read_bytes()
     k = len(lps)
     st = np.frombuffer(raw[:4 * k], np.int32)
