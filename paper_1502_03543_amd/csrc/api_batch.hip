@@ -19,6 +19,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kItersPerGraph = 4;  // default of lp_options.batch_graph_iters
+constexpr int kCompactMin = 8;     // no compaction below this many launched LPs
 
 struct Carver {
   char* base;
@@ -362,6 +363,65 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
   return LP_OK;
 }
 
+// Move the still-active LPs to the first descriptor slots (relative order
+// kept, so the largest still start first) and return their number and
+// largest m.  Descriptors, states and the slot -> caller map move together;
+// every other per-LP array is either addressed through the descriptor or
+// rebuilt at the start of each iteration.
+static hipError_t compact_active(lp_batch* h, int cur_count, int* active_out, int* max_m_out) {
+  hipStream_t s = h->st;
+  std::vector<BatchState> st(cur_count);
+  hipError_t e = hipMemcpyAsync(st.data(), h->state, sizeof(BatchState) * cur_count,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  std::vector<int> perm;
+  perm.reserve(cur_count);
+  for (int k = 0; k < cur_count; ++k)
+    if (st[k].status == LP_OK) perm.push_back(k);
+  const int active = (int)perm.size();
+  for (int k = 0; k < cur_count; ++k)
+    if (st[k].status != LP_OK) perm.push_back(k);
+  std::vector<BatchLP> lps(cur_count);
+  std::vector<BatchState> st2(cur_count);
+  std::vector<int> ord(cur_count);
+  int mm = 0;
+  for (int k = 0; k < cur_count; ++k) {
+    lps[k] = h->lps_h[perm[k]];
+    st2[k] = st[perm[k]];
+    ord[k] = h->order[perm[k]];
+    if (k < active) mm = std::max(mm, lps[k].m);
+  }
+  std::copy(lps.begin(), lps.end(), h->lps_h.begin());
+  std::copy(ord.begin(), ord.end(), h->order.begin());
+  e = hipMemcpyAsync(h->lps, h->lps_h.data(), sizeof(BatchLP) * cur_count, hipMemcpyHostToDevice,
+                     s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->state, st2.data(), sizeof(BatchState) * cur_count,
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  *active_out = active;
+  *max_m_out = mm;
+  return e;
+}
+
+// Capture graph_iters iterations of the first `count` descriptor slots into
+// one graph (nothing on the legacy default stream, which cannot be captured:
+// there the launches are issued directly).
+static hipError_t capture_iterations(lp_batch* h, const BatchArgs& a, int max_m,
+                                     hipGraph_t* graph, hipGraphExec_t* exec) {
+  *graph = nullptr;
+  *exec = nullptr;
+  if (h->st == nullptr) return hipSuccess;
+  hipError_t e = hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int k = 0; k < h->graph_iters; ++k) launch_batch_step(h->st, a, max_m, -1, nullptr);
+    e = hipStreamEndCapture(h->st, graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+  return e;
+}
+
 lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t* status,
                          int32_t* iters, int32_t* n_converged) {
   if (!h || max_iter < 0 || !(gap_tol >= 0)) return LP_ERR_INVALID_ARG;
@@ -369,27 +429,22 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
   BatchArgs a = h->args;
   a.tol = gap_tol;
   a.max_iter = max_iter;
-  // Capture graph_iters iterations into one graph and replay it.  The
-  // legacy default stream cannot be captured; there the same launches are
-  // issued directly.
+  // graph_iters iterations per replayed graph.  When the LPs still running
+  // are at most half of those launched for, they are moved to the first
+  // slots and the graph is captured again for them alone: the launches then
+  // cover fewer LPs, and only as many panel steps as the largest of them
+  // needs, so the tail of a ragged batch stops paying for finished LPs.
+  int cur_count = h->count, cur_max_m = h->max_m;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipError_t e = hipSuccess;
-  if (s != nullptr) {
-    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      for (int k = 0; k < h->graph_iters; ++k) launch_batch_step(s, a, h->max_m, -1, nullptr);
-      e = hipStreamEndCapture(s, &graph);
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  }
+  hipError_t e = capture_iterations(h, a, cur_max_m, &graph, &exec);
   int launches = 0;
   const int max_launches = max_iter / h->graph_iters + 2;
   while (e == hipSuccess) {
     if (exec) {
       e = hipGraphLaunch(exec, s);
     } else {
-      for (int k = 0; k < h->graph_iters; ++k) launch_batch_step(s, a, h->max_m, -1, nullptr);
+      for (int k = 0; k < h->graph_iters; ++k) launch_batch_step(s, a, cur_max_m, -1, nullptr);
       e = hipGetLastError();
     }
     int active = 0;
@@ -398,6 +453,18 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     ++launches;
     if (e != hipSuccess || active == 0 || launches > max_launches) break;
+    if (2 * active <= cur_count && cur_count > kCompactMin) {
+      int n_act = 0, mm = 0;
+      e = compact_active(h, cur_count, &n_act, &mm);
+      if (e != hipSuccess) break;
+      if (n_act == 0) break;
+      cur_count = n_act;
+      cur_max_m = mm;
+      a.count = cur_count;
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      e = capture_iterations(h, a, cur_max_m, &graph, &exec);
+    }
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);

@@ -127,6 +127,33 @@ def test_emulated_batch_matches_oracle(emu, tmp_path, tile):
         om += m
 
 
+def test_emulated_batch_compaction(emu, tmp_path):
+    """Twelve LPs of very different sizes: the batch is compacted (running
+    LPs moved to the first slots, the launches re-shaped for them) as the
+    small ones finish; every LP still matches the oracle's solve."""
+    lps = [lpgen.gen_lp(m, n, 40 + i) for i, (m, n) in enumerate(
+        [(6, 20), (90, 300), (8, 30), (12, 40), (70, 260), (5, 17), (10, 33), (16, 60),
+         (9, 28), (130, 420), (7, 25), (11, 35)])]
+    _write(tmp_path / "in.bin", lps)
+    _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0, 0)
+    raw = (tmp_path / "out.bin").read_bytes()
+    k = len(lps)
+    st = np.frombuffer(raw[:4 * k], np.int32)
+    it = np.frombuffer(raw[4 * k:8 * k], np.int32)
+    sn = sum(lp.A.shape[1] for lp in lps)
+    y = np.frombuffer(raw[8 * k:], np.float64)[sn:]
+    om = 0
+    for i, lp in enumerate(lps):
+        m = lp.A.shape[0]
+        ro = oracle.solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95, 1e-8, 200)
+        assert ro.status == oracle.CONVERGED and st[i] == 1, (i, st[i], ro.status_name)
+        assert it[i] == ro.iters, (i, it[i], ro.iters)
+        byo = lp.b @ ro.y
+        assert abs(lp.b @ y[om:om + m] - byo) <= 1e-9 * max(1.0, abs(byo))
+        om += m
+    assert len(set(it.tolist())) > 1  # the LPs finish at different iterations
+
+
 def test_emulated_batch_reverse_matches_oracle(emu, tmp_path):
     K = 3
     lps = _lps()[:3]
