@@ -129,6 +129,35 @@ def batch_variant(lpgen, solver, capi, torch, sample: int = 32) -> dict:
               "source": "autotune cache" if solver.tuned_batch_launch(bt.m, bt.n)
               else "library default"}
     bt.close()
+    # the same batch with the FP32 factor and FP64 refinement per LP
+    wm = solver.Batch(lps, alpha=0.95, precision="mixed")
+    wm.solve(1e-8, 200)
+    wm.close()
+    bm = solver.Batch(lps, alpha=0.95, precision="mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    resm = bm.solve(1e-8, 200)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    bm.close()
+    # untimed: which factor each step used (lp_batch_iterate reports it)
+    bi = solver.Batch(lps, alpha=0.95, precision="mixed")
+    n32 = n64 = 0
+    for _ in range(200):
+        st_i, info = bi.iterate(1e-8)
+        for e in info:
+            if e["k"] >= 0:
+                n32 += e["precision_used"] == capi.LP_PREC_MIXED
+                n64 += e["precision_used"] != capi.LP_PREC_MIXED
+        if not np.any(st_i == capi.LP_OK):
+            break
+    bi.close()
+    mixed = {"lps_per_s": len(lps) / tm, "ms": tm * 1e3,
+             "vs_fp64_batched": (len(lps) / tm) / (len(lps) / tb),
+             "n_converged": int(resm["n_converged"]),
+             "steps_with_fp32_factor": int(n32), "steps_with_fp64_factor": int(n64),
+             "note": "FP32 normal matrix and factor, up to 5 FP64 corrections per step, FP64 "
+                     "fallback per LP; FP64 below gap 1e-6"}
     dev = torch.device("cuda:0")
     hs = []
     for lp in lps[:sample]:
@@ -149,6 +178,7 @@ def batch_variant(lpgen, solver, capi, torch, sample: int = 32) -> dict:
         "batched_lps_per_s": len(lps) / tb,
         "batched_ms": tb * 1e3,
         "launch": launch,
+        "mixed_precision": mixed,
         "fp64_lp_by_lp_lps_per_s": sample / ts,
         "lp_by_lp_sample": f"single-LP solver on LPs 0..{sample - 1}, one after another",
         "speedup_vs_lp_by_lp": (len(lps) / tb) / (sample / ts),

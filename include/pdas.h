@@ -290,12 +290,20 @@ lp_status lp_destroy(lp_handle* h);
 /* a fixed sequence of launches (normal-matrix tiles, Cholesky panels and      */
 /* trailing updates of every LP at once, per-LP direction and step); several   */
 /* iterations are captured into one hipGraph and replayed.  LPs that stopped   */
-/* skip every launch.  FP64 only.                                              */
+/* skip every launch.  FP64, or mixed precision per LP (below).              */
 /* ------------------------------------------------------------------------- */
 typedef struct lp_batch lp_batch;
 
 /* Workspace bytes for a batch; m, n are host arrays of length count, each LP
- * needing 1 <= m_i < n_i (LP_ERR_SHAPE otherwise). */
+ * needing 1 <= m_i < n_i (LP_ERR_SHAPE otherwise).  Options: LP_METHOD_AFFINE
+ * and LP_SOLVER_CHOLESKY; precision LP_PREC_FP64 or LP_PREC_MIXED.  MIXED
+ * runs the single-LP mixed scheme per LP inside the captured iteration: an
+ * FP32 normal matrix and factor, up to refine_max (<= 16) FP64 corrections,
+ * and for an LP whose FP32 pivot fails, whose corrections stall or that does
+ * not converge, the FP64 factor in the same iteration and from then on (also
+ * once its gap is below mixed_switch_gap); no tape with MIXED.
+ * lp_batch_iterate reports per LP the factor used (precision_used) and the
+ * corrections taken.  Other options give LP_ERR_INVALID_ARG. */
 lp_status lp_batch_workspace_size(int32_t count, const int64_t* m, const int64_t* n,
                                   const lp_options* opt, size_t* bytes);
 

@@ -20,6 +20,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kItersPerGraph = 4;  // default of lp_options.batch_graph_iters
 constexpr int kCompactMin = 8;     // no compaction below this many launched LPs
+constexpr int kMaxBatchRefine = 16;  // largest lp_options.refine_max of a mixed batch
 
 struct Carver {
   char* base;
@@ -146,7 +147,7 @@ bool batch_shapes_ok(int32_t count, const int64_t* m, const int64_t* n) {
 void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
   const int count = h->count;
   h->lps_h.resize(count);
-  long vm = 0, vn = 0, moff = 0, toff = 0, doff = 0;
+  long vm = 0, vn = 0, moff = 0, toff = 0, doff = 0, a32 = 0, m32 = 0, vn4 = 0;
   const int tape_cap = h->opt.tape_capacity > 0 ? h->opt.tape_capacity : 0;
   for (int i = 0; i < count; ++i) {
     BatchLP& P = h->lps_h[i];
@@ -160,6 +161,14 @@ void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
     P.M_off = moff;
     P.tape_off = toff;
     P.diag_off = doff;
+    P.n4 = (P.n + 3) / 4 * 4;
+    P.ld32 = (P.m + 3) / 4 * 4;
+    P.a32_off = a32;
+    P.m32_off = m32;
+    P.vn4 = vn4;
+    a32 += (long)P.m * P.n4;
+    m32 += (long)P.ld32 * P.m;
+    vn4 += P.n4;
     doff += potrf_diag_elems(P.m);
     vm += P.m;
     vn += P.n;
@@ -211,6 +220,26 @@ void carve_batch(lp_batch* h, const int64_t* m, const int64_t* n, Carver& cv) {
   a.dpi = cv.take<long long>((long)count * a.nslice);
   a.dpf = cv.take<int>((long)count * a.nslice);
   h->bufptrs = cv.take<double>(6);  // x[2], y[2], s[2] pointers for get_iterate
+  a.mixed = h->opt.precision == LP_PREC_MIXED;
+  if (a.mixed) {
+    a.refine_tol = h->opt.refine_tol;
+    a.refine_max = h->opt.refine_max;
+    a.switch_gap = h->opt.mixed_switch_gap;
+    a.A32 = cv.take<float>(a32);
+    a.M32 = cv.take<float>(m32);
+    a.diag32 = cv.take<float>(doff);
+    a.sd32 = cv.take<float>(vn4);
+    a.r = cv.take<double>(vm);
+    a.delta = cv.take<double>(vm);
+    a.v = cv.take<double>(vn);
+    a.fp32_mode = cv.take<int>(count);
+    a.m32 = cv.take<int>(count);
+    a.go64 = cv.take<int>(count);
+    a.refm = cv.take<int>(count);
+    a.ref_status = cv.take<int>(count);
+    a.ref_steps = cv.take<int>(count);
+    a.ref_prev = cv.take<double>(count);
+  }
   if (tape_cap) {
     BatchAdj& g = h->adj;
     g.xb = cv.take<double>(vn);
@@ -247,7 +276,15 @@ lp_status lp_batch_workspace_size(int32_t count, const int64_t* m, const int64_t
   lp_options_default(&o);
   if (opt) o = *opt;
   if (!(o.alpha > 0.0 && o.alpha < 1.0) || o.tape_capacity < 0) return LP_ERR_INVALID_ARG;
-  if (o.precision != LP_PREC_FP64 || o.method != LP_METHOD_AFFINE) return LP_ERR_INVALID_ARG;
+  if (o.precision != LP_PREC_FP64 && o.precision != LP_PREC_MIXED) return LP_ERR_INVALID_ARG;
+  if (o.method != LP_METHOD_AFFINE) return LP_ERR_INVALID_ARG;
+  // mixed precision: the single-LP rules, no tape (the reverse sweep
+  // recomputes FP64 steps), at most kMaxBatchRefine corrections (each is
+  // three launches of every captured iteration)
+  if (o.precision == LP_PREC_MIXED &&
+      (!(o.refine_tol >= 0) || o.refine_max < 0 || o.refine_max > kMaxBatchRefine ||
+       !(o.mixed_switch_gap >= 0) || o.tape_capacity != 0))
+    return LP_ERR_INVALID_ARG;
   if (o.solver != LP_SOLVER_CHOLESKY || o.reserved != 0 || o.reserved2 != 0) return LP_ERR_INVALID_ARG;
   if (o.batch_tile != 0 && o.batch_tile != 32 && o.batch_tile != 64) return LP_ERR_INVALID_ARG;
   if (o.batch_graph_iters < 0 || o.batch_graph_iters > 16) return LP_ERR_INVALID_ARG;
@@ -353,6 +390,10 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
                      h->state);
   launch_batch_setup(s, count, h->lps, h->state, A_packed, a.c, a.x[0], a.y[0], a.s[0],
                      a.rd[0]);
+  if (a.mixed) {
+    launch_bmix_setup(s, count, h->max_m, h->lps, A_packed, const_cast<float*>(a.A32));
+    launch_fill_i32(s, a.fp32_mode, 1, count);
+  }
   e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
@@ -365,9 +406,10 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
 
 // Move the still-active LPs to the first descriptor slots (relative order
 // kept, so the largest still start first) and return their number and
-// largest m.  Descriptors, states and the slot -> caller map move together;
-// every other per-LP array is either addressed through the descriptor or
-// rebuilt at the start of each iteration.
+// largest m.  Descriptors, states, the slot -> caller map and (mixed
+// precision) the FP32-factor flags move together; every other per-LP array
+// is either addressed through the descriptor or rebuilt at the start of
+// each iteration.
 static hipError_t compact_active(lp_batch* h, int cur_count, int* active_out, int* max_m_out) {
   hipStream_t s = h->st;
   std::vector<BatchState> st(cur_count);
@@ -394,6 +436,17 @@ static hipError_t compact_active(lp_batch* h, int cur_count, int* active_out, in
   }
   std::copy(lps.begin(), lps.end(), h->lps_h.begin());
   std::copy(ord.begin(), ord.end(), h->order.begin());
+  // the FP32-factor flag of a mixed batch is per LP and persistent: it moves too
+  std::vector<int> f32(cur_count), f32p(cur_count);
+  int* f32d = h->args.fp32_mode;
+  if (f32d) {
+    e = hipMemcpyAsync(f32.data(), f32d, sizeof(int) * cur_count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < cur_count; ++k) f32p[k] = f32[perm[k]];
+    e = hipMemcpyAsync(f32d, f32p.data(), sizeof(int) * cur_count, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+  }
   e = hipMemcpyAsync(h->lps, h->lps_h.data(), sizeof(BatchLP) * cur_count, hipMemcpyHostToDevice,
                      s);
   if (e == hipSuccess)
@@ -453,6 +506,20 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     ++launches;
     if (e != hipSuccess || active == 0 || launches > max_launches) break;
+    bool recapture = false;
+    if (a.mixed) {
+      // once no LP may use the FP32 factor any more, the iteration drops
+      // the FP32 and refinement launches
+      std::vector<int> f32(cur_count);
+      e = hipMemcpyAsync(f32.data(), a.fp32_mode, sizeof(int) * cur_count,
+                         hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) break;
+      if (std::none_of(f32.begin(), f32.end(), [](int v) { return v != 0; })) {
+        a.mixed = 0;
+        recapture = true;
+      }
+    }
     if (2 * active <= cur_count && cur_count > kCompactMin) {
       int n_act = 0, mm = 0;
       e = compact_active(h, cur_count, &n_act, &mm);
@@ -461,6 +528,9 @@ lp_status lp_batch_solve(lp_batch* h, double gap_tol, int32_t max_iter, int32_t*
       cur_count = n_act;
       cur_max_m = mm;
       a.count = cur_count;
+      recapture = true;
+    }
+    if (recapture) {
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);
       e = capture_iterations(h, a, cur_max_m, &graph, &exec);
@@ -510,6 +580,12 @@ lp_status lp_batch_iterate(lp_batch* h, double gap_tol, int32_t* status, lp_iter
   if (e == hipSuccess)
     e = hipMemcpyAsync(minp.data(), a.minp, sizeof(unsigned long long) * count,
                        hipMemcpyDeviceToHost, s);
+  std::vector<int> rst(count, 3), rsteps(count, 0);
+  if (a.mixed && e == hipSuccess)
+    e = hipMemcpyAsync(rst.data(), a.ref_status, sizeof(int) * count, hipMemcpyDeviceToHost, s);
+  if (a.mixed && e == hipSuccess)
+    e = hipMemcpyAsync(rsteps.data(), a.ref_steps, sizeof(int) * count, hipMemcpyDeviceToHost,
+                       s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return LP_ERR_DEVICE;
   for (int k = 0; k < count; ++k) {
@@ -536,8 +612,10 @@ lp_status lp_batch_iterate(lp_batch* h, double gap_tol, int32_t* status, lp_iter
     double mp;
     std::memcpy(&mp, &minp[k], sizeof(double));
     o.min_pivot = ran ? mp : 0.0;
-    o.precision_used = LP_PREC_FP64;
-    o.refine_steps = 0;
+    // FP32 factor when its refinement converged (status 1), else FP64
+    const bool used32 = ran && rst[k] == 1;
+    o.precision_used = used32 ? LP_PREC_MIXED : LP_PREC_FP64;
+    o.refine_steps = ran && rst[k] != 3 ? rsteps[k] : 0;
     o.refine_resid = 0.0;
   }
   return LP_OK;

@@ -311,7 +311,9 @@ __global__ __launch_bounds__(256) void k_brhs(BatchArgs a) {
 }
 
 // Breakdown check, then L z = rhs and L^T dy = z.
-__global__ __launch_bounds__(256) void k_btrsv(BatchArgs a, int k, int* err) {
+// (go_main, when given, is the stepping flag to clear on a breakdown when
+// a.go is a narrower mask: the FP64 factor of a mixed-precision batch.)
+__global__ __launch_bounds__(256) void k_btrsv(BatchArgs a, int k, int* err, int* go_main) {
   __shared__ double lds[4 * BT + BT * (BT + 1)];
   const int lp = blockIdx.x;
   if (!a.go[lp]) return;
@@ -325,6 +327,7 @@ __global__ __launch_bounds__(256) void k_btrsv(BatchArgs a, int k, int* err) {
         atomicOr(err, 1);
       }
       a.go[lp] = 0;
+      if (go_main) go_main[lp] = 0;
     }
     return;
   }
@@ -742,6 +745,190 @@ __global__ __launch_bounds__(256) void k_batch_rd(int count, const BatchLP* lps,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision (lp_options.precision == LP_PREC_MIXED), per LP as in the
+// single-LP solver: an FP32 normal matrix (sqrt(d) on both operands) and
+// FP32 factor, widened to FP64 for the solves, then up to refine_max FP64
+// corrections on the matrix-free residual r = rhs - A (d o (A^T dy)); an
+// LP whose FP32 pivot fails, whose corrections stall (a correction not
+// below half the previous one) or that has not converged after refine_max
+// corrections takes the FP64 factor in the same iteration and keeps it.
+// Convergence: ||delta||_inf / ||dy||_inf <= tol, or, once the corrections
+// contract by q < 1/2, ||delta|| q / (1 - q) / ||dy|| <= tol.
+enum { kRefRun = 0, kRefOk = 1, kRefFail = 2, kRefNone = 3 };
+
+// A32 with rows padded to n4 (zeros beyond n): one workgroup per row group.
+__global__ __launch_bounds__(256) void k_bmix_a32(const BatchLP* __restrict__ lps,
+                                                   const double* __restrict__ A, float* A32) {
+  const int lp = blockIdx.y;
+  const BatchLP P = lps[lp];
+  const int i = blockIdx.x;
+  if (i >= P.m) return;
+  const double* src = A + P.a_off + (long)i * P.n;
+  float* dst = const_cast<float*>(A32) + P.a32_off + (long)i * P.n4;
+  for (int j = threadIdx.x; j < P.n4; j += 256) dst[j] = j < P.n ? (float)src[j] : 0.f;
+}
+
+// Which factor each stepping LP takes this iteration; sqrt(d) in FP32.
+__global__ __launch_bounds__(256) void k_bmix_begin(BatchArgs a) {
+  const int lp = blockIdx.x;
+  const BatchLP P = a.lps[lp];
+  __shared__ int s_m32;
+  if (threadIdx.x == 0) {
+    const int go = a.go[lp];
+    if (go && a.fp32_mode[lp] && !(a.state[lp].gap >= a.switch_gap)) a.fp32_mode[lp] = 0;
+    const int m32 = go && a.fp32_mode[lp];
+    a.m32[lp] = m32;
+    a.go64[lp] = go && !m32;
+    a.refm[lp] = 0;
+    a.ref_status[lp] = m32 ? kRefRun : kRefNone;
+    a.ref_steps[lp] = 0;
+    a.ref_prev[lp] = INFINITY;
+    s_m32 = m32;
+  }
+  __syncthreads();
+  if (!s_m32) return;
+  const double* d = a.d + P.vn;
+  float* sd = a.sd32 + P.vn4;
+  for (int j = threadIdx.x; j < P.n4; j += 256) sd[j] = j < P.n ? (float)sqrt(d[j]) : 0.f;
+}
+
+// After the FP32 factor: a failed pivot ends the FP32 attempt; otherwise L
+// is widened into the FP64 matrix and the first solve gives dy.
+__global__ __launch_bounds__(256) void k_bmix_solve0(BatchArgs a) {
+  __shared__ double lds[4 * BT + BT * (BT + 1)];
+  const int lp = blockIdx.x;
+  if (!a.m32[lp]) return;
+  const BatchLP P = a.lps[lp];
+  if (a.fail[lp] != INT_MAX) {
+    if (threadIdx.x == 0) a.ref_status[lp] = kRefFail;
+    return;
+  }
+  const float* L32 = a.M32 + P.m32_off;
+  double* M = a.M + P.M_off;
+  const int m = P.m;
+  for (long e = threadIdx.x; e < (long)m * m; e += 256) {
+    const int r = (int)(e / m), c = (int)(e % m);
+    if (c <= r) M[(long)r * P.ldm + c] = (double)L32[(long)r * P.ld32 + c];
+  }
+  __syncthreads();
+  wg_trsv_fwd(m, M, P.ldm, a.rhs + P.vm, a.z + P.vm, lds);
+  wg_trsv_bwd(m, M, P.ldm, a.z + P.vm, a.dy + P.vm, lds);
+  if (threadIdx.x == 0) a.refm[lp] = 1;
+}
+
+// v = d o (A^T dy): one workgroup per LP and 256-column slice.
+__global__ __launch_bounds__(256) void k_bref_v(BatchArgs a) {
+  const int lp = blockIdx.y, sl = blockIdx.x;
+  if (!a.refm[lp]) return;
+  const BatchLP P = a.lps[lp];
+  const int j = sl * 256 + threadIdx.x;
+  if (j >= P.n) return;
+  const double* acol = a.A + P.a_off + j;
+  const double* dy = a.dy + P.vm;
+  double g = 0.0;
+  int i = 0;
+  for (; i + 8 <= P.m; i += 8) {
+    double av[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) av[u] = acol[(long)(i + u) * P.n];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g += av[u] * dy[i + u];
+  }
+  for (; i < P.m; ++i) g += acol[(long)i * P.n] * dy[i];
+  a.v[P.vn + j] = a.d[P.vn + j] * g;
+}
+
+// r = rhs - A v: one wavefront per row, four rows per workgroup.
+__global__ __launch_bounds__(256) void k_bref_r(BatchArgs a) {
+  const int lp = blockIdx.y;
+  if (!a.refm[lp]) return;
+  const BatchLP P = a.lps[lp];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= P.m) return;  // whole wavefronts
+  const double* arow = a.A + P.a_off + (long)i * P.n;
+  const double* v = a.v + P.vn;
+  double acc = 0.0;
+  for (int j = lane; j < P.n; j += 64) acc += arow[j] * v[j];
+  acc = wsum(acc);
+  if (lane == 0) a.r[P.vm + i] = a.rhs[P.vm + i] - acc;
+}
+
+// delta = L^-T L^-1 r, dy += delta, then the convergence test.
+__global__ __launch_bounds__(256) void k_bref_solve(BatchArgs a) {
+  __shared__ double lds[4 * BT + BT * (BT + 1)];
+  __shared__ double sh[4];
+  const int lp = blockIdx.x;
+  if (!a.refm[lp]) return;
+  const BatchLP P = a.lps[lp];
+  const double* M = a.M + P.M_off;
+  double* delta = a.delta + P.vm;
+  double* dy = a.dy + P.vm;
+  wg_trsv_fwd(P.m, M, P.ldm, a.r + P.vm, a.z + P.vm, lds);
+  wg_trsv_bwd(P.m, M, P.ldm, a.z + P.vm, delta, lds);
+  __syncthreads();
+  double dn = 0.0, yn = 0.0;
+  for (int i = threadIdx.x; i < P.m; i += 256) {
+    const double y2 = dy[i] + delta[i];
+    dy[i] = y2;
+    dn = fmax(dn, fabs(delta[i]));
+    yn = fmax(yn, fabs(y2));
+  }
+  // max norms over the workgroup (a NaN poisons them: fmax would drop it)
+  int bad = 0;
+  for (int i = threadIdx.x; i < P.m; i += 256) bad |= !isfinite(delta[i]) | !isfinite(dy[i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    dn = fmax(dn, __shfl_xor(dn, o, 64));
+    yn = fmax(yn, __shfl_xor(yn, o, 64));
+  }
+  __shared__ double s_dn[4], s_yn[4];
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  if ((threadIdx.x & 63) == 0) {
+    s_dn[threadIdx.x >> 6] = dn;
+    s_yn[threadIdx.x >> 6] = yn;
+  }
+  __syncthreads();
+  if (bad) atomicOr(&s_bad, 1);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  (void)sh;
+  dn = fmax(fmax(s_dn[0], s_dn[1]), fmax(s_dn[2], s_dn[3]));
+  yn = fmax(fmax(s_yn[0], s_yn[1]), fmax(s_yn[2], s_yn[3]));
+  const int step = a.ref_steps[lp];
+  a.ref_steps[lp] = step + 1;
+  int stt = kRefRun;
+  if (s_bad || !(yn > 0)) {
+    stt = kRefFail;
+  } else {
+    const double rel = dn / yn;
+    if (rel <= a.refine_tol) {
+      stt = kRefOk;
+    } else if (step > 0) {
+      const double q = dn / a.ref_prev[lp];
+      if (!(q < 0.5)) stt = kRefFail;                            // stagnation
+      else if (rel * q / (1.0 - q) <= a.refine_tol) stt = kRefOk;
+    }
+  }
+  a.ref_prev[lp] = dn;
+  a.ref_status[lp] = stt;
+  if (stt != kRefRun) a.refm[lp] = 0;
+}
+
+// FP32 attempts that did not converge take the FP64 factor now and from now on.
+__global__ void k_bmix_end(BatchArgs a) {
+  const int lp = blockIdx.x * 256 + threadIdx.x;
+  if (lp >= a.count || !a.m32[lp]) return;
+  a.refm[lp] = 0;
+  if (a.ref_status[lp] == kRefOk) return;
+  a.ref_status[lp] = kRefFail;
+  a.fp32_mode[lp] = 0;
+  a.go64[lp] = 1;
+  a.fail[lp] = INT_MAX;
+  a.minp[lp] = 0x7ff0000000000000ull;
+}
+
 }  // namespace
 
 void launch_batch_step(hipStream_t st, const BatchArgs& a, int max_m, int k,
@@ -751,13 +938,22 @@ void launch_batch_step(hipStream_t st, const BatchArgs& a, int max_m, int k,
   if (k < 0) hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, st, a.active);
   hipLaunchKernelGGL(k_bbegin, dim3(count), dim3(256), 0, st, a, k);
   hipLaunchKernelGGL(k_brhs, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a);
-  launch_bsyrk_normal(st, count, max_m, a.tile, a.lps, a.go, a.A, a.d, a.M);
-  for (int p = 0; p < max_m; p += BT) {
-    launch_bpotrf_panel(st, count, max_m, a.lps, a.go, a.M, a.diag, p, a.fail, a.minp);
-    launch_bsyrk_trailing(st, count, max_m, a.tile, a.lps, a.go, a.M, p);
+  // the FP64 factor: every stepping LP, or in a mixed-precision forward
+  // iteration the LPs that do not (or no longer) use the FP32 factor
+  BatchArgs a64 = a;
+  int* go_main = nullptr;
+  if (a.mixed && k < 0) {
+    launch_bmix_factor(st, a, max_m);
+    a64.go = a.go64;
+    go_main = a.go;
   }
-  launch_bdiag_to_m(st, count, max_m, a.lps, a.go, a.M, a.diag);
-  hipLaunchKernelGGL(k_btrsv, dim3(count), dim3(256), 0, st, a, k, err);
+  launch_bsyrk_normal(st, count, max_m, a.tile, a.lps, a64.go, a.A, a.d, a.M);
+  for (int p = 0; p < max_m; p += BT) {
+    launch_bpotrf_panel(st, count, max_m, a.lps, a64.go, a.M, a.diag, p, a.fail, a.minp);
+    launch_bsyrk_trailing(st, count, max_m, a.tile, a.lps, a64.go, a.M, p);
+  }
+  launch_bdiag_to_m(st, count, max_m, a.lps, a64.go, a.M, a.diag);
+  hipLaunchKernelGGL(k_btrsv, dim3(count), dim3(256), 0, st, a64, k, err, go_main);
   hipLaunchKernelGGL(k_bdir, dim3(a.nslice, count), dim3(256), 0, st, a, k);
   hipLaunchKernelGGL(k_bdir_fin, dim3(cdiv(count, 256)), dim3(256), 0, st, a, k, err);
   if (k < 0) hipLaunchKernelGGL(k_bstep, dim3(count), dim3(256), 0, st, a);
@@ -769,6 +965,29 @@ void launch_batch_step(hipStream_t st, const BatchArgs& a, int max_m, int k,
                        k);
     hipLaunchKernelGGL(k_badj_yb, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a, *adj, k);
   }
+}
+
+void launch_bmix_setup(hipStream_t st, int count, int max_m, const BatchLP* lps, const double* A,
+                       float* A32) {
+  hipLaunchKernelGGL(k_bmix_a32, dim3(max_m, count), dim3(256), 0, st, lps, A, A32);
+}
+
+void launch_bmix_factor(hipStream_t st, const BatchArgs& a, int max_m) {
+  const int count = a.count;
+  hipLaunchKernelGGL(k_bmix_begin, dim3(count), dim3(256), 0, st, a);
+  launch_bsyrk_normal_f32(st, count, max_m, a.tile, a.lps, a.m32, a.A32, a.sd32, a.M32);
+  for (int p = 0; p < max_m; p += BT) {
+    launch_bpotrf_panel_f32(st, count, max_m, a.lps, a.m32, a.M32, a.diag32, p, a.fail, a.minp);
+    launch_bsyrk_trailing_f32(st, count, max_m, a.tile, a.lps, a.m32, a.M32, p);
+  }
+  launch_bdiag_to_m_f32(st, count, max_m, a.lps, a.m32, a.M32, a.diag32);
+  hipLaunchKernelGGL(k_bmix_solve0, dim3(count), dim3(256), 0, st, a);
+  for (int q = 0; q < a.refine_max; ++q) {
+    hipLaunchKernelGGL(k_bref_v, dim3(a.nslice, count), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_bref_r, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_bref_solve, dim3(count), dim3(256), 0, st, a);
+  }
+  hipLaunchKernelGGL(k_bmix_end, dim3(cdiv(count, 256)), dim3(256), 0, st, a);
 }
 
 void launch_babar(hipStream_t st, int count, int max_tiles, const BatchLP* lps,

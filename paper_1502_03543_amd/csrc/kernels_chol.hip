@@ -863,6 +863,33 @@ __global__ __launch_bounds__(256) void k_bpotrf_panel(const BatchLP* __restrict_
                               minp_bits + lp, lds);
 }
 
+// Batched FP32 panel step at column p (mixed precision): the single-LP FP32
+// panel routine on M32_i for the LPs whose flag is set.
+__global__ __launch_bounds__(256) void k_bpotrf_panel_f32(const BatchLP* __restrict__ lps,
+                                                           const int* __restrict__ go,
+                                                           float* M32, float* diag32, int p,
+                                                           int* fail,
+                                                           unsigned long long* minp_bits) {
+  const int lp = blockIdx.y;
+  const BatchLP P = lps[lp];
+  if (!go[lp] || p >= P.m) return;
+  const int below = P.m - p - min(NB, P.m - p);
+  if ((int)blockIdx.x > (below + kRowsPerWG - 1) / kRowsPerWG) return;
+  potrf_panel_body<float>(P.m, P.m, M32 + P.m32_off, P.ld32, p, blockIdx.x,
+                          diag32 + P.diag_off + (long)(p / NB) * NB * NB, fail + lp,
+                          minp_bits + lp);
+}
+
+__global__ __launch_bounds__(256) void k_bdiag_to_m_f32(const BatchLP* __restrict__ lps,
+                                                         const int* __restrict__ go, float* M32,
+                                                         const float* diag32) {
+  const int lp = blockIdx.y;
+  if (!go[lp]) return;
+  const BatchLP P = lps[lp];
+  if ((int)blockIdx.x * NB >= P.m) return;
+  diag_to_m<float>(P.m, M32 + P.m32_off, P.ld32, diag32 + P.diag_off, blockIdx.x);
+}
+
 // Batched diagonal blocks into M: LP = blockIdx.y, block blockIdx.x.
 __global__ __launch_bounds__(256) void k_bdiag_to_m(const BatchLP* __restrict__ lps,
                                                      const int* __restrict__ go, double* Mpool,
@@ -981,6 +1008,21 @@ void launch_bdiag_to_m(hipStream_t st, int count, int max_m, const BatchLP* lps,
                        double* Mpool, const double* diagpool) {
   hipLaunchKernelGGL(k_bdiag_to_m, dim3(cdiv(max_m, NB), count), dim3(256), 0, st, lps, go, Mpool,
                      diagpool);
+}
+
+void launch_bpotrf_panel_f32(hipStream_t st, int count, int max_m, const BatchLP* lps,
+                             const int* go, float* M32, float* diag32, int p, int* fail,
+                             unsigned long long* minp_bits) {
+  const int below = max_m - p - NB;
+  const int gx = 1 + (below > 0 ? cdiv(below, kRowsPerWG) : 0);
+  hipLaunchKernelGGL(k_bpotrf_panel_f32, dim3(gx, count), dim3(256), 0, st, lps, go, M32, diag32,
+                     p, fail, minp_bits);
+}
+
+void launch_bdiag_to_m_f32(hipStream_t st, int count, int max_m, const BatchLP* lps,
+                           const int* go, float* M32, const float* diag32) {
+  hipLaunchKernelGGL(k_bdiag_to_m_f32, dim3(cdiv(max_m, NB), count), dim3(256), 0, st, lps, go,
+                     M32, diag32);
 }
 
 }  // namespace pdas

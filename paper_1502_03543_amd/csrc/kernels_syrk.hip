@@ -47,24 +47,22 @@ __global__ __launch_bounds__(256) void k_syrk_f64(int mm, int K, const double* _
 // A wavefront owns a (16 R) x (16 R) output (R x R blocks); a workgroup of
 // 2 x 2 wavefronts owns a BM = 32 R square tile.  LDS layout as in the FP64
 // kernel (blocks of 4 k by 16 rows), so every operand read is lane-linear.
+// One lower tile t (linear index over the lower triangle of BM-tiles) and
+// K split `split` of the FP32 product; the whole workgroup takes part.
+// lds: the caller's [2 stages][2 operands][BM * KC] floats.
 template <int R, int KC, bool SCALE>
-__global__ __launch_bounds__(256) void k_syrk_f32(int mm, int K, const float* __restrict__ X,
-                                                  long ldx, const float* __restrict__ w,
-                                                  float* __restrict__ C, long ldc, int sub,
-                                                  int ntiles, int per_xcd, int kchunk,
-                                                  float* __restrict__ part) {
+__device__ __forceinline__ void syrk_f32_tile(int mm, int K, const float* __restrict__ X,
+                                              long ldx, const float* __restrict__ w,
+                                              float* __restrict__ C, long ldc, int sub, int t,
+                                              int split, int ntiles, int kchunk,
+                                              float* __restrict__ part,
+                                              float (*lds)[2][32 * R * KC]) {
   constexpr int BM = 32 * R;
   constexpr int QPR = KC / 4;              // float4 groups per row per stage
   constexpr int QUADS = BM * QPR / 256;    // groups per thread per operand
-  __shared__ float lds[2][2][BM * KC];
-
-  const int b = blockIdx.x;
-  const int t = (b & 7) * per_xcd + (b >> 3);
-  if (t >= ntiles) return;
   int ti, tj;
   tile_coords(t, ti, tj);
   const int row0 = ti * BM, col0 = tj * BM;
-  const int split = blockIdx.y;
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
   const int nst = (kend - kbeg + KC - 1) / KC;
@@ -171,6 +169,20 @@ __global__ __launch_bounds__(256) void k_syrk_f32(int mm, int K, const float* __
       }
 }
 
+template <int R, int KC, bool SCALE>
+__global__ __launch_bounds__(256) void k_syrk_f32(int mm, int K, const float* __restrict__ X,
+                                                  long ldx, const float* __restrict__ w,
+                                                  float* __restrict__ C, long ldc, int sub,
+                                                  int ntiles, int per_xcd, int kchunk,
+                                                  float* __restrict__ part) {
+  __shared__ float lds[2][2][32 * R * KC];
+  const int b = blockIdx.x;
+  const int t = (b & 7) * per_xcd + (b >> 3);
+  if (t >= ntiles) return;
+  syrk_f32_tile<R, KC, SCALE>(mm, K, X, ldx, w, C, ldc, sub, t, blockIdx.y, ntiles, kchunk, part,
+                              lds);
+}
+
 template <int BM>
 __global__ __launch_bounds__(256) void k_syrk_reduce_f32(int mm, float* __restrict__ C, long ldc,
                                                          int sub, int ntiles, int splits,
@@ -233,6 +245,48 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing(const BatchLP* __restric
   __shared__ double2 lds2[syrk_tile_lds2<BM / 8, 32>()];
   syrk_f64_tile<BM / 8, BM / 32, 32, false, true>(mm, 64, X, P.ldm, nullptr, X + 64, P.ldm, 1, t,
                                                   ntiles, 0, 1, 64, nullptr, lds2);
+}
+
+// Batched FP32 normal matrices (mixed precision): LP = blockIdx.y, lower
+// BM-tile blockIdx.x of M32_i = (A32_i diag(sd_i)) (A32_i diag(sd_i))^T over
+// the padded rows (n4 = n rounded up to 4, zero padding), for the LPs whose
+// flag is set.
+template <int R>
+__global__ __launch_bounds__(256) void k_bsyrk_normal_f32(const BatchLP* __restrict__ lps,
+                                                           const int* __restrict__ go,
+                                                           const float* __restrict__ A32,
+                                                           const float* __restrict__ sd32,
+                                                           float* __restrict__ M32) {
+  const int lp = blockIdx.y;
+  if (!go[lp]) return;
+  const BatchLP P = lps[lp];
+  constexpr int BM = 32 * R;
+  const int nt = (P.m + BM - 1) / BM, ntiles = nt * (nt + 1) / 2;
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
+  __shared__ float lds[2][2][32 * R * 32];
+  syrk_f32_tile<R, 32, true>(P.m, P.n4, A32 + P.a32_off, P.n4, sd32 + P.vn4, M32 + P.m32_off,
+                             P.ld32, 0, t, 0, ntiles, P.n4, nullptr, lds);
+}
+
+// Batched FP32 trailing update after the panel at column p.
+template <int R>
+__global__ __launch_bounds__(256) void k_bsyrk_trailing_f32(const BatchLP* __restrict__ lps,
+                                                             const int* __restrict__ go,
+                                                             float* __restrict__ M32, int p) {
+  const int lp = blockIdx.y;
+  if (!go[lp]) return;
+  const BatchLP P = lps[lp];
+  const int mm = P.m - p - 64;
+  if (mm <= 0) return;
+  constexpr int BM = 32 * R;
+  const int nt = (mm + BM - 1) / BM, ntiles = nt * (nt + 1) / 2;
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
+  float* X = M32 + P.m32_off + (long)(p + 64) * P.ld32 + p;
+  __shared__ float lds[2][2][32 * R * 32];
+  syrk_f32_tile<R, 32, false>(mm, 64, X, P.ld32, nullptr, X + 64, P.ld32, 1, t, 0, ntiles, 64,
+                              nullptr, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -659,6 +713,30 @@ void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const
   else
     hipLaunchKernelGGL(k_bsyrk_trailing<64>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
                        lps, go, Mpool, p);
+}
+
+void launch_bsyrk_normal_f32(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
+                             const int* go, const float* A32, const float* sd32, float* M32) {
+  const int nt = cdiv(max_m, tile);
+  if (tile == 32)
+    hipLaunchKernelGGL(k_bsyrk_normal_f32<1>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
+                       lps, go, A32, sd32, M32);
+  else
+    hipLaunchKernelGGL(k_bsyrk_normal_f32<2>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
+                       lps, go, A32, sd32, M32);
+}
+
+void launch_bsyrk_trailing_f32(hipStream_t st, int count, int max_m, int tile,
+                               const BatchLP* lps, const int* go, float* M32, int p) {
+  const int mm = max_m - p - 64;
+  if (mm <= 0) return;
+  const int nt = cdiv(mm, tile);
+  if (tile == 32)
+    hipLaunchKernelGGL(k_bsyrk_trailing_f32<1>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
+                       lps, go, M32, p);
+  else
+    hipLaunchKernelGGL(k_bsyrk_trailing_f32<2>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
+                       lps, go, M32, p);
 }
 
 }  // namespace pdas

@@ -206,6 +206,12 @@ struct BatchLP {
   long M_off;     // element offset of M_i (ldm x m) in the matrix pool
   long tape_off;  // element offset of LP i's tape
   long diag_off;  // element offset of LP i's diagonal-block scratch
+  // mixed precision (FP32 factor): rows of A32 and sqrt(d) padded to n4 =
+  // n rounded up to 4 with zeros; M32 is ld32 x m, ld32 = m rounded up to 4
+  long a32_off;   // element offset of A32_i in the FP32 matrix pool
+  long m32_off;   // element offset of M32_i
+  long vn4;       // element offset of LP i's padded n-vectors (sqrt(d) in FP32)
+  int ld32, n4;
 };
 
 struct BatchState {
@@ -246,6 +252,20 @@ struct BatchArgs {
   double* dpv;          // per LP and slice: the slice's ratio-test maximum,
   long long* dpi;       //   its first maximiser
   int* dpf;             //   and flags (1 nonzero direction, 2 non-finite ratio)
+  // mixed precision (lp_options.precision == LP_PREC_MIXED; null otherwise)
+  int mixed;
+  double refine_tol, switch_gap;
+  int refine_max;
+  const float* A32;     // FP32 copies of the A_i (padded rows)
+  float *M32, *diag32, *sd32;
+  double *r, *delta, *v;  // refinement residual, correction, d o (A^T dy)
+  int* fp32_mode;       // per LP: FP32 factor still allowed (cleared for good)
+  int* m32;             // per LP: FP32 factor tried in this iteration
+  int* go64;            // per LP: FP64 factor in this iteration
+  int* refm;            // per LP: refinement still running
+  int* ref_status;      // per LP: 0 running, 1 converged, 2 failed, 3 none
+  int* ref_steps;       // per LP: corrections taken in this iteration
+  double* ref_prev;     // per LP: previous correction's max norm
 };
 
 // Adjoint pools of a batch (packed like the forward vectors; Abar like A).
@@ -273,6 +293,21 @@ void launch_batch_setup(hipStream_t st, int count, const BatchLP* lps, BatchStat
                         const double* Ap, const double* c, const double* x, const double* y,
                         const double* s, double* rd);
 // batched building blocks (kernels_syrk.hip, kernels_chol.hip)
+// mixed precision of the batch (kernels_batch_mixed.hip): the FP32 copies
+// of A (setup), then per iteration the FP32 factor of the LPs that try it,
+// up to refine_max FP64 corrections, and the FP64 factor for the others
+void launch_bmix_setup(hipStream_t st, int count, int max_m, const BatchLP* lps, const double* A,
+                       float* A32);
+void launch_bmix_factor(hipStream_t st, const BatchArgs& a, int max_m);
+void launch_bsyrk_normal_f32(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
+                             const int* go, const float* A32, const float* sd32, float* M32);
+void launch_bsyrk_trailing_f32(hipStream_t st, int count, int max_m, int tile,
+                               const BatchLP* lps, const int* go, float* M32, int p);
+void launch_bpotrf_panel_f32(hipStream_t st, int count, int max_m, const BatchLP* lps,
+                             const int* go, float* M32, float* diag32, int p, int* fail,
+                             unsigned long long* minp_bits);
+void launch_bdiag_to_m_f32(hipStream_t st, int count, int max_m, const BatchLP* lps,
+                           const int* go, float* M32, const float* diag32);
 // tile: 32 or 64 (the edge of the lower tiles)
 void launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                          const int* go, const double* A, const double* d, double* Mpool);

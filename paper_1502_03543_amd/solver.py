@@ -296,10 +296,12 @@ class Batch:
 
     ``problems`` is a list of objects with numpy fields A (m_i x n_i), b, c,
     x0, y0, s0; they are packed on the host, uploaded once, and solved by the
-    batched kernel.  FP64."""
+    batched kernels, in FP64 or (precision="mixed") with the FP32 factor and
+    FP64 refinement per LP."""
 
     def __init__(self, problems, alpha=0.95, tape_capacity=0, device="cuda", batch_tile=None,
-                 batch_graph_iters=None):
+                 batch_graph_iters=None, precision="fp64", refine_max=5, refine_tol=2.0 ** -46,
+                 mixed_switch_gap=1e-6):
         import numpy as np
 
         self.count = len(problems)
@@ -323,8 +325,10 @@ class Batch:
             tuned = tuned_batch_launch(self.m, self.n)
             batch_tile = tuned.get("batch_tile", 0)
             batch_graph_iters = tuned.get("batch_graph_iters", 0)
-        self.opts = options(alpha=alpha, tape_capacity=tape_capacity,
-                            batch_tile=batch_tile or 0, batch_graph_iters=batch_graph_iters or 0)
+        self.opts = options(alpha=alpha, tape_capacity=tape_capacity, precision=precision,
+                            refine_max=refine_max, refine_tol=refine_tol,
+                            mixed_switch_gap=mixed_switch_gap, batch_tile=batch_tile or 0,
+                            batch_graph_iters=batch_graph_iters or 0)
         I64 = C.c_int64 * self.count
         self._m, self._n = I64(*self.m), I64(*self.n)
         self._aoff, self._vom, self._von = I64(*self.a_off), I64(*self.v_off_m), I64(*self.v_off_n)

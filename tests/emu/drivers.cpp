@@ -15,7 +15,7 @@
 //                                     than one metadata chunk; 1: uniform,
 //                                     half full), then the check's verdict on
 //                                     broken copies of the CSR
-//   emu batch <in> <out> <max_iter> <tape> [tile]
+//   emu batch <in> <out> <max_iter> <tape> [tile] [mixed]
 //                                     batched solve of the LPs in <in>; with a
 //                                     tape, also the reverse sweep
 #include <cmath>
@@ -155,7 +155,8 @@ static int run_trsv(int m) {
   return 0;
 }
 
-static int run_batch(const char* in, const char* out, int max_iter, int tape, int tile) {
+static int run_batch(const char* in, const char* out, int max_iter, int tape, int tile,
+                     int mixed) {
   FILE* f = fopen(in, "rb");
   if (!f) return 2;
   int count = 0;
@@ -184,6 +185,7 @@ static int run_batch(const char* in, const char* out, int max_iter, int tape, in
   lp_options_default(&opt);
   opt.tape_capacity = tape;
   opt.batch_tile = tile;
+  if (mixed) opt.precision = LP_PREC_MIXED;
   size_t bytes = 0;
   int st = lp_batch_workspace_size(count, m.data(), n.data(), &opt, &bytes);
   if (st != LP_OK) return 3;
@@ -386,7 +388,8 @@ int main(int argc, char** argv) {
   if (argc >= 5 && !strcmp(argv[1], "sparse"))
     return run_sparse(atoi(argv[2]), atoi(argv[3]), atoi(argv[4]));
   if (argc >= 6 && !strcmp(argv[1], "batch"))
-    return run_batch(argv[2], argv[3], atoi(argv[4]), atoi(argv[5]), argc >= 7 ? atoi(argv[6]) : 0);
+    return run_batch(argv[2], argv[3], atoi(argv[4]), atoi(argv[5]), argc >= 7 ? atoi(argv[6]) : 0,
+                     argc >= 8 ? atoi(argv[7]) : 0);
   fprintf(stderr, "usage: emu chol <m> | emu batch <in> <out> <max_iter> <tape>\n");
   return 1;
 }

@@ -169,3 +169,56 @@ def test_batch_iterate_matches_oracle(torch_dev):
         if len(stopped) == len(lps):
             break
     assert len(stopped) == len(lps)
+
+
+def test_batch_mixed_precision_matches_oracle(torch_dev):
+    """precision="mixed": every LP against the FP64 oracle (status, K, b^T y
+    within 1e-9); early iterations use the FP32 factor (refinement
+    converged within refine_max corrections), late ones FP64."""
+    from paper_1502_03543_amd import solver
+    lps = lpgen.gen_batch(24, first_seed=300)
+    bt = solver.Batch(lps, alpha=0.95, precision="mixed")
+    used32 = np.zeros(len(lps), dtype=int)
+    used64 = np.zeros(len(lps), dtype=int)
+    for it in range(200):
+        st, info = bt.iterate(1e-8)
+        for i, e in enumerate(info):
+            if e["k"] < 0:
+                continue
+            assert 0 <= e["refine_steps"] <= 5
+            if e["precision_used"] == capi.LP_PREC_MIXED:
+                used32[i] += 1
+            else:
+                used64[i] += 1
+        if not np.any(st == capi.LP_OK):
+            break
+    print("FP32 iterations per LP:", used32.tolist(), "FP64:", used64.tolist(), flush=True)
+    assert used32.sum() > 0 and np.all(used64 > 0)
+    its = bt.iterates()
+    for i, lp in enumerate(lps):
+        _oracle_check(lp, st[i], used32[i] + used64[i], *its[i])
+
+
+def test_batch_mixed_precision_512(torch_dev):
+    """The 512-LP batch in mixed precision against the FP64 oracle's record:
+    the same statuses, b^T y within 1e-9 relative for every LP, iteration
+    counts equal for all but a few LPs (FP32 rounding may move a late
+    iterate across the gap threshold by one step)."""
+    import json
+    import os
+    from paper_1502_03543_amd import solver
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batch512_seed0.json")) as f:
+        gold = json.load(f)["lps"]
+    lps = lpgen.gen_batch(512, first_seed=0)
+    bt = solver.Batch(lps, alpha=0.95, precision="mixed")
+    res = bt.solve(1e-8, 200)
+    its = bt.iterates()
+    off = 0
+    for i, lp in enumerate(lps):
+        g = gold[i]
+        assert capi.status_string(res["status"][i]) == "LP_" + g["status"], (i, g["status"])
+        x, y, s = its[i]
+        assert abs(lp.b @ y - g["dual_obj"]) <= 1e-9 * max(1.0, abs(g["dual_obj"])), i
+        off += res["iters"][i] != g["iters"]
+    print("LPs whose iteration count differs from FP64:", off, flush=True)
+    assert off <= 5

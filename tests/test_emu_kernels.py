@@ -127,15 +127,43 @@ def test_emulated_batch_matches_oracle(emu, tmp_path, tile):
         om += m
 
 
-def test_emulated_batch_compaction(emu, tmp_path):
+def test_emulated_batch_mixed_precision(emu, tmp_path):
+    """The batch with the FP32 factor and FP64 refinement per LP: statuses,
+    iteration counts and b^T y as the FP64 oracle; the LP with a zero row
+    fails its FP32 pivot, falls back to FP64 and breaks down there."""
+    lps = _lps()
+    _write(tmp_path / "in.bin", lps)
+    _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0, 0, 1)
+    raw = (tmp_path / "out.bin").read_bytes()
+    k = len(lps)
+    st = np.frombuffer(raw[:4 * k], np.int32)
+    it = np.frombuffer(raw[4 * k:8 * k], np.int32)
+    sn = sum(lp.A.shape[1] for lp in lps)
+    y = np.frombuffer(raw[8 * k:], np.float64)[sn:]
+    names = {1: "CONVERGED", 2: "OPTIMAL_PSI1", -4: "ERR_BREAKDOWN"}
+    om = 0
+    for i, lp in enumerate(lps):
+        m = lp.A.shape[0]
+        ro = oracle.solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95, 1e-8, 200)
+        assert names.get(int(st[i])) == ro.status_name, (i, st[i], ro.status_name)
+        assert it[i] == ro.iters
+        if ro.status == oracle.CONVERGED:
+            byo = lp.b @ ro.y
+            assert abs(lp.b @ y[om:om + m] - byo) <= 1e-9 * max(1.0, abs(byo))
+        om += m
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_emulated_batch_compaction(emu, tmp_path, mixed):
     """Twelve LPs of very different sizes: the batch is compacted (running
     LPs moved to the first slots, the launches re-shaped for them) as the
-    small ones finish; every LP still matches the oracle's solve."""
+    small ones finish, in FP64 and with the per-LP FP32 factor (whose flags
+    move with their LPs); every LP still matches the oracle's solve."""
     lps = [lpgen.gen_lp(m, n, 40 + i) for i, (m, n) in enumerate(
         [(6, 20), (90, 300), (8, 30), (12, 40), (70, 260), (5, 17), (10, 33), (16, 60),
          (9, 28), (130, 420), (7, 25), (11, 35)])]
     _write(tmp_path / "in.bin", lps)
-    _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0, 0)
+    _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0, 0, mixed)
     raw = (tmp_path / "out.bin").read_bytes()
     k = len(lps)
     st = np.frombuffer(raw[:4 * k], np.int32)
