@@ -531,6 +531,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--mixed-compare", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variant", choices=("batched", "sparse", "adjoint", "woodbury"),
+                    help="run only this variant and print its JSON (for profiling)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -542,6 +544,18 @@ def main():
         return
     if args.mixed_compare:
         mixed_compare()
+        return
+    if args.variant:
+        import torch
+
+        from paper_1502_03543_amd import capi, lpgen, solver
+
+        capi.load()
+        run = {"batched": lambda: batch_variant(lpgen, solver, capi, torch),
+               "sparse": lambda: sparse_variant(lpgen, solver, capi, torch),
+               "adjoint": lambda: adjoint_variant(lpgen, solver, capi, torch, False),
+               "woodbury": lambda: woodbury_variant(lpgen, solver, capi, torch)}[args.variant]
+        print(json.dumps({"variant": args.variant, **run()}))
         return
 
     import numpy as np
