@@ -54,7 +54,12 @@ __device__ bool wait_flag(int* flag, DevInfo* info, int* s_abort) {
     }
   }
   __syncthreads();
-  if (*s_abort) return false;
+  const bool abort = *s_abort != 0;
+  // every thread has the verdict before thread 0, running ahead into the
+  // next wait, can set the flag on a timeout (the others would then leave
+  // the loop one wait early and meet a different barrier)
+  __syncthreads();
+  if (abort) return false;
   // each thread acquires, so its later loads see the producer's stores
   (void)__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
   return true;

@@ -9,15 +9,18 @@
 #define EMU_UNPOISON(p, n) ((void)0)
 #endif
 
-dim3 threadIdx;
-dim3 blockIdx, blockDim, gridDim;
-EmuBarrier g_block_bar;
-EmuBarrier g_wave_bar[kEmuWaves];
-uint64_t g_wave_buf[kEmuWaves][64];
-uint64_t g_wave_buf2[kEmuWaves][64];
-long g_barrier_count = 0;
-char* g_emu_dyn_lds = nullptr;
-long g_progress = 0;
+#include <atomic>
+#include <thread>
+
+thread_local dim3 threadIdx;
+thread_local dim3 blockIdx, blockDim, gridDim;
+thread_local EmuBarrier g_block_bar;
+thread_local EmuBarrier g_wave_bar[kEmuWaves];
+thread_local uint64_t g_wave_buf[kEmuWaves][64];
+thread_local uint64_t g_wave_buf2[kEmuWaves][64];
+thread_local long g_barrier_count = 0;
+thread_local char* g_emu_dyn_lds = nullptr;
+thread_local long g_progress = 0;
 
 extern "C" void emu_switch(void** save_sp, void* load_sp);
 asm(R"(
@@ -45,11 +48,11 @@ emu_switch:
 namespace {
 constexpr size_t kStack = 256 * 1024;
 struct Fiber { void* sp = nullptr; bool done = false; };
-void* g_main_sp = nullptr;
-std::vector<Fiber> g_f;
-std::vector<char> g_stacks;
-std::function<void()> g_body;
-int g_cur = -1;
+thread_local void* g_main_sp = nullptr;
+thread_local std::vector<Fiber> g_f;
+thread_local std::vector<char> g_stacks;
+thread_local std::function<void()> g_body;
+thread_local int g_cur = -1;
 extern "C" void emu_entry() {
   const int t = g_cur;
   threadIdx = dim3(t, 0, 0);
@@ -112,4 +115,43 @@ void emu_run_block(int nt, std::function<void()> body) {
       stuck = 0;
     }
   }
+}
+
+int emu_interleave() {
+  static const int k = [] {
+    const char* e = std::getenv("EMU_INTERLEAVE");
+    const int v = e ? std::atoi(e) : 1;
+    return v < 1 ? 1 : (v > 64 ? 64 : v);
+  }();
+  return k;
+}
+
+void emu_run_grid(dim3 grid, dim3 block, size_t shm, const std::function<void()>& body) {
+  const long nblocks = (long)grid.x * grid.y;
+  const int workers = (int)std::min<long>(emu_interleave(), nblocks);
+  std::atomic<long> next{0};
+  auto work = [&] {
+    blockDim = block;
+    gridDim = grid;
+    char* dyn = shm ? new char[shm] : nullptr;
+    g_emu_dyn_lds = dyn;
+    for (long b = next.fetch_add(1); b < nblocks; b = next.fetch_add(1)) {
+      blockIdx = dim3((unsigned)(b % grid.x), (unsigned)(b / grid.x), 0);
+      if (dyn) std::memset(dyn, 0xff, shm);
+      emu_run_block(block.x, body);
+    }
+    delete[] dyn;
+    g_emu_dyn_lds = nullptr;
+  };
+  if (workers <= 1) {
+    work();
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int w = 0; w < workers; ++w) pool.emplace_back(work);
+  for (auto& t : pool) t.join();
+}
+
+void emu_sleep() {
+  if (emu_interleave() > 1) std::this_thread::sleep_for(std::chrono::microseconds(20));
 }

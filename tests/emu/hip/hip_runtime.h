@@ -1,8 +1,13 @@
 // CPU emulation of the subset of HIP that the library's kernels use, for
 // checking kernel logic on the host (test infrastructure only).
 //
-// Workgroups run one at a time; the threads of a workgroup are fibers on one
-// OS thread (tests/emu/emu_runtime.cpp).  A fiber runs until it waits at a
+// Workgroups run one at a time, or (EMU_INTERLEAVE=K in the environment) K
+// at a time on K OS threads, each taking the next workgroup in launch order;
+// the threads of a workgroup are fibers on one OS thread
+// (tests/emu/emu_runtime.cpp), and everything a workgroup owns (its thread
+// and block indices, barriers, LDS) is thread-local, so concurrent
+// workgroups interleave at arbitrary points and meet only in memory and in
+// the (real) atomics.  A fiber runs until it waits at a
 // barrier, so __syncthreads, wavefront exchanges (__shfl, __shfl_xor,
 // readlane) and the matrix-core instructions (every lane of the wavefront
 // contributes its operands, then each lane reads its result) follow the
@@ -28,7 +33,7 @@
 #define __device__
 #define __host__
 #define __forceinline__ inline
-#define __shared__ static
+#define __shared__ static thread_local
 #define __launch_bounds__(...)
 #define HIP_SYMBOL(x) x
 
@@ -49,8 +54,8 @@ struct dim3 {
   unsigned x, y, z;
   dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
-extern dim3 threadIdx;
-extern dim3 blockIdx, blockDim, gridDim;
+extern thread_local dim3 threadIdx;
+extern thread_local dim3 blockIdx, blockDim, gridDim;
 
 // fiber scheduler (one OS thread): a fiber runs until it waits at a barrier
 void emu_yield();
@@ -68,13 +73,13 @@ struct EmuBarrier {
   void wait();
   void wait_at(const char* file, int line);
 };
-extern EmuBarrier g_block_bar;
+extern thread_local EmuBarrier g_block_bar;
 constexpr int kEmuWaves = 16;  // up to 1024 threads per workgroup
-extern EmuBarrier g_wave_bar[kEmuWaves];
-extern uint64_t g_wave_buf[kEmuWaves][64];
-extern uint64_t g_wave_buf2[kEmuWaves][64];
-extern long g_barrier_count;
-extern long g_progress;
+extern thread_local EmuBarrier g_wave_bar[kEmuWaves];
+extern thread_local uint64_t g_wave_buf[kEmuWaves][64];
+extern thread_local uint64_t g_wave_buf2[kEmuWaves][64];
+extern thread_local long g_barrier_count;
+extern thread_local long g_progress;
 
 inline void EmuBarrier::wait() {
   const long g = gen;
@@ -108,7 +113,11 @@ inline void __threadfence() {}
 // points the kernels mark explicit synchronisation points of the wavefront
 inline void __builtin_amdgcn_wave_barrier() { g_wave_bar[threadIdx.x >> 6].wait(); }
 inline void __builtin_amdgcn_sched_barrier(int) {}
-inline void __builtin_amdgcn_s_sleep(int) {}
+// with workgroups running at once, a polling thread gives its OS thread
+// away for a moment (the producer it waits for runs on another one), so a
+// spin limit counts real time as on the hardware rather than host loop trips
+void emu_sleep();
+inline void __builtin_amdgcn_s_sleep(int) { emu_sleep(); }
 inline void __builtin_amdgcn_s_waitcnt(int) {}
 
 template <typename T>
@@ -221,10 +230,12 @@ inline emu_f4 __builtin_amdgcn_mfma_f32_16x16x4f32(float a, float b, emu_f4 c, i
 #define __HIP_MEMORY_SCOPE_WORKGROUP 3
 #define __HIP_MEMORY_SCOPE_AGENT 4
 #endif
-inline int atomicAdd(int* p, int v) { int o = *p; *p += v; return o; }
-inline int atomicOr(int* p, int v) { int o = *p; *p |= v; return o; }
-inline int atomicMin(int* p, int v) { int o = *p; if (v < o) *p = v; return o; }
-inline unsigned long long atomicMin(unsigned long long* p, unsigned long long v) { auto o = *p; if (v < o) *p = v; return o; }
+inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline int atomicMin(int* p, int v) { return __atomic_fetch_min(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned long long atomicMin(unsigned long long* p, unsigned long long v) {
+  return __atomic_fetch_min(p, v, __ATOMIC_SEQ_CST);
+}
 inline int __double2loint(double d) { return (int)(uint32_t)emu_bits(d); }
 inline int __double2hiint(double d) { return (int)(uint32_t)(emu_bits(d) >> 32); }
 inline double __hiloint2double(int hi, int lo) { return emu_from<double>(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo); }
@@ -240,21 +251,14 @@ void emu_run_block(int nt, std::function<void()> body);
 // launch's size, refilled with NaN bytes before every workgroup (LDS holds
 // no data from an earlier workgroup), so reads beyond it are reported and
 // reads before a write show up as NaN
-extern char* g_emu_dyn_lds;
+extern thread_local char* g_emu_dyn_lds;
+int emu_interleave();  // workgroups run at once (EMU_INTERLEAVE, default 1)
+// runs blocks first .. first + count - 1 (launch order, x fastest) of the
+// grid on `workers` OS threads; each worker has its own LDS block
+void emu_run_grid(dim3 grid, dim3 block, size_t shm, const std::function<void()>& body);
 template <typename... KA, typename... A>
 inline void emu_launch(void (*k)(KA...), dim3 grid, dim3 block, size_t shm, A... args) {
-  blockDim = block;
-  gridDim = grid;
-  char* dyn = shm ? new char[shm] : nullptr;
-  g_emu_dyn_lds = dyn;
-  for (unsigned by = 0; by < grid.y; ++by)
-    for (unsigned bx = 0; bx < grid.x; ++bx) {
-      blockIdx = dim3(bx, by, 0);
-      if (dyn) std::memset(dyn, 0xff, shm);
-      emu_run_block(block.x, [=] { k(args...); });
-    }
-  delete[] dyn;
-  g_emu_dyn_lds = nullptr;
+  emu_run_grid(grid, block, shm, [=] { k(args...); });
 }
 #define hipLaunchKernelGGL(k, grid, block, shm, st, ...) emu_launch(k, dim3(grid), dim3(block), (size_t)(shm), __VA_ARGS__)
 enum { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };

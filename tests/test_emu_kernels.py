@@ -35,9 +35,10 @@ def emu():
     return build_emu.build()
 
 
-def _run(exe, *args, timeout=600):
+def _run(exe, *args, timeout=600, interleave=1):
+    env = dict(ENV, EMU_INTERLEAVE=str(interleave))
     p = subprocess.run([exe, *map(str, args)], capture_output=True, text=True, timeout=timeout,
-                       env=ENV)
+                       env=env)
     assert p.returncode == 0, p.stdout[-2000:] + p.stderr[-4000:]
     return p.stdout
 
@@ -207,3 +208,36 @@ def test_emulated_batch_reverse_matches_oracle(emu, tmp_path):
         ao += m * n
         vm += m
         vn += n
+
+
+@pytest.mark.parametrize("case", ["trsv", "chol", "syrk", "sparse", "batch"])
+def test_emulated_kernels_interleaved(emu, tmp_path, case):
+    """Workgroups run four or eight at a time on their own OS threads, so
+    they interleave at arbitrary points: the ticketed triangular solves
+    poll blocks that are still running, the fused Cholesky step's panel and
+    update workgroups overlap, the batched solver's workgroups take LPs
+    concurrently.  Results as in the sequential runs; any barrier reached
+    unevenly aborts the run."""
+    if case == "trsv":
+        r = json.loads(_run(emu, "trsv", 700, interleave=8).strip().splitlines()[-1])
+        assert r["err_flag"] == 0 and r["fwd_rel_err"] <= 1e-13 and r["bwd_rel_err"] <= 1e-13, r
+    elif case == "chol":
+        r = json.loads(_run(emu, "chol", 300, interleave=4).strip().splitlines()[-1])
+        assert r["fail"] == -1 and r["factor_rel_err"] <= 1e-13 and r["solve_rel_err"] <= 1e-13, r
+    elif case == "syrk":
+        r = json.loads(_run(emu, "syrk", 150, 302, 0, 0, interleave=4).strip().splitlines()[-1])
+        assert r["rel_err"] <= 1e-14, r
+    elif case == "sparse":
+        r = json.loads(_run(emu, "sparse", 2200, 2600, 0, interleave=8).strip().splitlines()[-1])
+        assert r["flags"] == 0 and r["csc_bad"] == 0 and r["syrk_rel_err"] <= 1e-14, r
+    else:
+        lps = _lps()
+        _write(tmp_path / "in.bin", lps)
+        _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0, 0, 1, interleave=4)
+        raw = (tmp_path / "out.bin").read_bytes()
+        k = len(lps)
+        st = np.frombuffer(raw[:4 * k], np.int32)
+        it = np.frombuffer(raw[4 * k:8 * k], np.int32)
+        for i, lp in enumerate(lps):
+            ro = oracle.solve(lp.A, lp.b, lp.c, lp.x0, lp.y0, lp.s0, 0.95, 1e-8, 200)
+            assert it[i] == ro.iters and (st[i] == 1) == (ro.status == oracle.CONVERGED), i
