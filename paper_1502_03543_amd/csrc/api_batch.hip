@@ -391,7 +391,7 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
   launch_batch_setup(s, count, h->lps, h->state, A_packed, a.c, a.x[0], a.y[0], a.s[0],
                      a.rd[0]);
   if (a.mixed) {
-    launch_bmix_setup(s, count, h->max_m, h->lps, A_packed, const_cast<float*>(a.A32));
+    launch_bmix_setup(s, count, h->max_m, h->lps, A_packed, a.A32);
     launch_fill_i32(s, a.fp32_mode, 1, count);
   }
   e = hipStreamSynchronize(s);

@@ -765,7 +765,7 @@ __global__ __launch_bounds__(256) void k_bmix_a32(const BatchLP* __restrict__ lp
   const int i = blockIdx.x;
   if (i >= P.m) return;
   const double* src = A + P.a_off + (long)i * P.n;
-  float* dst = const_cast<float*>(A32) + P.a32_off + (long)i * P.n4;
+  float* dst = A32 + P.a32_off + (long)i * P.n4;
   for (int j = threadIdx.x; j < P.n4; j += 256) dst[j] = j < P.n ? (float)src[j] : 0.f;
 }
 
@@ -857,7 +857,6 @@ __global__ __launch_bounds__(256) void k_bref_r(BatchArgs a) {
 // delta = L^-T L^-1 r, dy += delta, then the convergence test.
 __global__ __launch_bounds__(256) void k_bref_solve(BatchArgs a) {
   __shared__ double lds[4 * BT + BT * (BT + 1)];
-  __shared__ double sh[4];
   const int lp = blockIdx.x;
   if (!a.refm[lp]) return;
   const BatchLP P = a.lps[lp];
@@ -893,7 +892,6 @@ __global__ __launch_bounds__(256) void k_bref_solve(BatchArgs a) {
   if (bad) atomicOr(&s_bad, 1);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  (void)sh;
   dn = fmax(fmax(s_dn[0], s_dn[1]), fmax(s_dn[2], s_dn[3]));
   yn = fmax(fmax(s_yn[0], s_yn[1]), fmax(s_yn[2], s_yn[3]));
   const int step = a.ref_steps[lp];

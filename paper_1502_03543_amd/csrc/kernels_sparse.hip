@@ -7,7 +7,7 @@
 //   A w        : G lanes per row of A (CSR),
 //   A^T [v, u] : G lanes per column of A (CSC), both products at once,
 // with G = 16 or 64 lanes chosen from the mean run length, and the normal
-// matrix M = A D A^T (dense lower; the Cholesky stays dense): workgroup i
+// matrix M = A D A^T (dense lower; the Cholesky stays dense): one wavefront
 // forms row i as the sum over the entries a_ik of row i of (d_k a_ik) times
 // the part of column k with rows j <= i, accumulated in an LDS row of
 // length i + 1.  The work is sum_i sum_{k in row i} |{j <= i : a_jk != 0}|
@@ -21,9 +21,6 @@
 
 namespace pdas {
 namespace {
-
-constexpr int kSpCH = 256;    // entries of row i per metadata chunk
-constexpr int kSpCap = 2048;  // staged products per group
 
 template <int G>
 __device__ inline double group_sum(double v) {
@@ -189,112 +186,76 @@ __global__ __launch_bounds__(256) void k_sp_gemv_t(long n, const int64_t* __rest
   }
 }
 
-// Row i of M (j <= i), rows taken largest first.  The entries of row i are
-// read in chunks of kSpCH: per entry e = (i, k) the scale u_e = d_k a_ik and
-// the run of column k with rows <= i (it ends at (i, k) itself, whose CSC
-// position map[e] gives); runs are staged in LDS in groups of at most kSpCap
-// products, all loads of a group issued at once, then added into the row
-// accumulator one entry after another (within an entry the rows j are
-// distinct, so its lanes never collide).  An entry whose run alone exceeds
-// the stage is added straight from the CSC.
-__global__ __launch_bounds__(256) void k_sp_syrk(long m, const int64_t* __restrict__ rp,
-                                                 const int* __restrict__ ci,
-                                                 const double* __restrict__ v,
-                                                 const int64_t* __restrict__ cp,
-                                                 const int* __restrict__ ri,
-                                                 const double* __restrict__ cv,
-                                                 const int* __restrict__ map,
-                                                 const double* __restrict__ d, double* M,
-                                                 long ldm) {
+// Row i of M (j <= i), one wavefront per row, rows taken largest first.
+// The entries e = (i, k) of row i are read 64 at a time, lane t holding
+// entry t's scale u = d_k a_ik and the run of column k with rows <= i (it
+// ends at (i, k) itself, whose CSC position map[e] gives); then entry after
+// entry, in increasing k, the lanes add u a_jk into the LDS row accumulator
+// over the run (rows j distinct within a run, so lanes never collide).  A
+// wavefront's LDS accesses take effect in program order, so the entries
+// need no barrier between them, and the next entry's run is loaded while
+// the current one is added.
+__global__ __launch_bounds__(64) void k_sp_syrk(long m, const int64_t* __restrict__ rp,
+                                                const int* __restrict__ ci,
+                                                const double* __restrict__ v,
+                                                const int64_t* __restrict__ cp,
+                                                const int* __restrict__ ri,
+                                                const double* __restrict__ cv,
+                                                const int* __restrict__ map,
+                                                const double* __restrict__ d, double* M,
+                                                long ldm) {
   extern __shared__ double lds[];
-  double* acc = lds;                 // m (i + 1 used)
-  double* su = acc + m;              // kSpCH
-  double* stv = su + kSpCH;          // kSpCap
-  int64_t* sp0 = reinterpret_cast<int64_t*>(stv + kSpCap);  // kSpCH
-  int* slen = reinterpret_cast<int*>(sp0 + kSpCH);          // kSpCH
-  int* soff = slen + kSpCH;                                  // kSpCH + 1
-  int* stj = soff + kSpCH + 1;                               // kSpCap
+  double* acc = lds;  // m (i + 1 used)
   const long i = m - 1 - blockIdx.x;
-  const int tid = threadIdx.x;
-  for (long j = tid; j <= i; j += 256) acc[j] = 0.0;
+  const int lane = threadIdx.x;
+  for (long j = lane; j <= i; j += 64) acc[j] = 0.0;
   const int64_t e0 = rp[i], e1 = rp[i + 1];
-  for (int64_t eb = e0; eb < e1; eb += kSpCH) {
-    const int ne = (int)min((int64_t)kSpCH, e1 - eb);
-    __syncthreads();  // the previous chunk's metadata is no longer read
-    if (tid < ne) {
-      const int64_t e = eb + tid;
+  for (int64_t eb = e0; eb < e1; eb += 64) {
+    const int ne = (int)min((int64_t)64, e1 - eb);
+    double u_l = 0.0;
+    long p0_l = 0;
+    int len_l = 0;
+    if (lane < ne) {
+      const int64_t e = eb + lane;
       const int k = ci[e];
-      const int64_t p0 = cp[k];
-      su[tid] = d[k] * v[e];
-      sp0[tid] = p0;
-      slen[tid] = (int)(map[e] - p0 + 1);
+      p0_l = (long)cp[k];
+      u_l = d[k] * v[e];
+      len_l = (int)(map[e] - p0_l + 1);
     }
-    __syncthreads();
-    if (tid == 0) {
-      int run = 0;
-      soff[0] = 0;
-      for (int q = 0; q < ne; ++q) {
-        run += slen[q];
-        soff[q + 1] = run;
+    // entry 0 of the chunk: its run's first 64 entries
+    long p0 = __shfl(p0_l, 0, 64);
+    int len = __shfl(len_l, 0, 64);
+    int rj = lane < len ? ri[p0 + lane] : 0;
+    double rv = lane < len ? cv[p0 + lane] : 0.0;
+    for (int q = 0; q < ne; ++q) {
+      const double u = __shfl(u_l, q, 64);
+      const long p0c = p0;
+      const int lenc = len;
+      const int rjc = rj;
+      const double rvc = rv;
+      // the next entry's run, in flight while this one is added
+      if (q + 1 < ne) {
+        p0 = __shfl(p0_l, q + 1, 64);
+        len = __shfl(len_l, q + 1, 64);
+        rj = lane < len ? ri[p0 + lane] : 0;
+        rv = lane < len ? cv[p0 + lane] : 0.0;
       }
-    }
-    __syncthreads();
-    int g0 = 0;
-    while (g0 < ne) {
-      // largest g1 in (g0, ne] with soff[g1] - soff[g0] <= kSpCap, else g0 + 1
-      const int base = soff[g0];
-      int lo = g0 + 1, hi = ne;
-      if (soff[lo] - base <= kSpCap) {
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (soff[mid] - base <= kSpCap) lo = mid;
-          else hi = mid - 1;
-        }
-      }
-      const int g1 = lo;
-      const int total = soff[g1] - base;
-      if (total <= kSpCap) {
-        for (int p = tid; p < total; p += 256) {
-          // the entry q of [g0, g1) whose run holds product p
-          int a = g0, b = g1 - 1;
-          while (a < b) {
-            const int mid = (a + b + 1) >> 1;
-            if (soff[mid] - base <= p) a = mid;
-            else b = mid - 1;
-          }
-          const int64_t sidx = sp0[a] + (p - (soff[a] - base));
-          stj[p] = ri[sidx];
-          stv[p] = su[a] * cv[sidx];
-        }
-        __syncthreads();
-        for (int q = g0; q < g1; ++q) {
-          const int o = soff[q] - base, len = slen[q];
-          for (int t = tid; t < len; t += 256) acc[stj[o + t]] += stv[o + t];
-          __syncthreads();
-        }
-      } else {
-        const int64_t p0 = sp0[g0];
-        const int len = slen[g0];
-        const double u = su[g0];
-        for (int t = tid; t < len; t += 256) acc[ri[p0 + t]] += u * cv[p0 + t];
-        __syncthreads();
-      }
-      g0 = g1;
+      if (lane < lenc) acc[rjc] += u * rvc;
+      for (int t = 64 + lane; t < lenc; t += 64) acc[ri[p0c + t]] += u * cv[p0c + t];
     }
   }
-  __syncthreads();
+  // every lane's last additions precede the reads below (in issue order on
+  // the hardware; marked so for the compiler and the host emulation)
+  __builtin_amdgcn_wave_barrier();
   double* Mi = M + i * ldm;
-  for (long j = tid; j <= i; j += 256) Mi[j] = acc[j];
+  for (long j = lane; j <= i; j += 64) Mi[j] = acc[j];
 }
 
 inline bool wide_runs(long nnz, long runs) { return runs > 0 && nnz >= 48 * runs; }
 
 }  // namespace
 
-size_t sp_syrk_lds_bytes(long m) {
-  return (size_t)m * sizeof(double) + kSpCH * (sizeof(double) + sizeof(int64_t) + sizeof(int)) +
-         (kSpCH + 1) * sizeof(int) + kSpCap * (sizeof(double) + sizeof(int));
-}
+size_t sp_syrk_lds_bytes(long m) { return (size_t)m * sizeof(double); }
 
 bool sp_fits(long m) { return sp_syrk_lds_bytes(m) <= kSparseMaxLds; }
 
@@ -350,7 +311,7 @@ void launch_sp_gemv_t(hipStream_t st, long n, long nnz, const int64_t* cp, const
 void launch_sp_syrk(hipStream_t st, long m, const int64_t* rp, const int* ci, const double* v,
                     const int64_t* cp, const int* ri, const double* cv, const int* map,
                     const double* d, double* M, long ldm) {
-  hipLaunchKernelGGL(k_sp_syrk, dim3(m), dim3(256), sp_syrk_lds_bytes(m), st, m, rp, ci, v, cp,
+  hipLaunchKernelGGL(k_sp_syrk, dim3(m), dim3(64), sp_syrk_lds_bytes(m), st, m, rp, ci, v, cp,
                      ri, cv, map, d, M, ldm);
 }
 

@@ -256,7 +256,7 @@ struct BatchArgs {
   int mixed;
   double refine_tol, switch_gap;
   int refine_max;
-  const float* A32;     // FP32 copies of the A_i (padded rows)
+  float* A32;           // FP32 copies of the A_i (padded rows)
   float *M32, *diag32, *sd32;
   double *r, *delta, *v;  // refinement residual, correction, d o (A^T dy)
   int* fp32_mode;       // per LP: FP32 factor still allowed (cleared for good)

@@ -74,9 +74,8 @@ def test_emulated_triangular_solves(emu, m):
 def test_emulated_sparse_kernels(emu, m, n, pattern):
     """CSR check, CSC build, both products and the sparse normal matrix.
     Pattern 0 reaches every branch of the normal-matrix kernel: a row of 300
-    entries (two metadata chunks), runs staged in several groups, and a
-    dense column whose run exceeds the stage for rows >= 2048 (added straight
-    from the CSC); pattern 1 takes the 64-lane products."""
+    entries (five 64-entry chunks), runs longer than a wavefront (the dense
+    column), empty rows and columns; pattern 1 takes the 64-lane products."""
     r = json.loads(_run(emu, "sparse", m, n, pattern).strip().splitlines()[-1])
     assert r["flags"] == 0 and r["csc_bad"] == 0 and r["upper_touched"] == 0, r
     assert r["gemv_n_rel_err"] <= 1e-15 and r["gemv_t_rel_err"] <= 1e-15, r
