@@ -799,20 +799,47 @@ __global__ __launch_bounds__(256) void k_chol_step(int mr, int mc, double* __res
 
 // Update of the next panel's columns q .. q + NB - 1 (all rows from q) with
 // the factor columns kcol .. kcol + K - 1 (K = 64: the panel just factored;
-// K = 256: the group of four just finished): the first two 32-wide tile
-// columns of that update.  This update sits on the critical path between two
-// panels, so it uses 32 x 32 tiles: four times the workgroups of 64 x 64
-// tiles, each with a quarter of the work.  Workgroup b takes tile (0, 0) for
-// b = 0, else ((b + 1) / 2, (b + 1) % 2).
+// K = 256: the group of four just finished).  This update sits on the
+// critical path between two panels, so it is cut fine and kept short: 32 x
+// 32 tiles (workgroup b takes tile (0, 0) for b = 0, else ((b + 1) / 2,
+// (b + 1) % 2)), each wavefront a 16 x 16 block on the 16 x 16 x 4 FP64
+// instruction with its operands loaded straight into registers (no LDS, no
+// barrier), 64 factor columns per round with every load of the round
+// issued at once; the accumulators start from C and the row operand is
+// negated, so the result is C - L_r L_c^T.
 constexpr int kCol0BM = 32;
 __global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ M, long ld, int q,
                                                    int kcol, int K) {
-  __shared__ double2 lds2[syrk_tile_lds2<4, 32>()];
   const int b = blockIdx.x;
   const int ti = (b + 1) / 2, tj = b == 0 ? 0 : (b + 1) % 2;
-  syrk_f64_tile<4, 1, 32, false, true>(mr - q, K, M + (long)q * ld + kcol, ld, nullptr,
-                                       M + (long)q * ld + q, ld, 1, ti * (ti + 1) / 2 + tj, 0, 0,
-                                       1, K, nullptr, lds2);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = q + kCol0BM * ti + 16 * (wv >> 1);  // the wavefront's block rows
+  const int c0 = q + kCol0BM * tj + 16 * (wv & 1);   // and columns
+  if (c0 > r0 + 15 || r0 >= mr) return;              // above the diagonal, or below the matrix
+  const double* pa = M + (long)min(r0 + li, mr - 1) * ld + kcol + lk;
+  const double* pb = M + (long)min(c0 + li, mr - 1) * ld + kcol + lk;
+  mf4 acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int gr = min(r0 + lk + 4 * v, mr - 1), gc = min(c0 + li, gr);
+    acc[v] = M[(long)gr * ld + gc];
+  }
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    double a[16], bb[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      a[s] = -pa[k0 + 4 * s];
+      bb[s] = pb[k0 + 4 * s];
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bb[s], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int gr = r0 + lk + 4 * v, gc = c0 + li;
+    if (gr < mr && gc <= gr) M[(long)gr * ld + gc] = acc[v];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_potrf_panel_f32(int mr, int mc, float* __restrict__ M,
