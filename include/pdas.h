@@ -129,7 +129,10 @@ typedef struct lp_options {
   int32_t method;          /* lp_method (default LP_METHOD_AFFINE)               */
   int32_t solver;          /* lp_solver (default LP_SOLVER_CHOLESKY)             */
   int32_t batch_tile;      /* lp_batch_*: normal-matrix and trailing-update tile
-                              edge, 0 (library's choice: 64), 32 or 64; see
+                              edge, 0 (library's choice: 64), 32, 64 or 128
+                              (128: FP64 normal matrix on 128 x 128 tiles of
+                              eight wavefronts; trailing updates and the FP32
+                              normal matrix then use 64); see
                               paper_1502_03543_amd/autotune.py.  Ignored by the
                               single-LP calls (which accept only these values) */
   int32_t batch_graph_iters; /* lp_batch_solve: iterations captured per

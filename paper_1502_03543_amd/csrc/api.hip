@@ -269,7 +269,8 @@ bool valid_opts(const lp_options* o) {
   if (o->method != LP_METHOD_AFFINE && o->method != LP_METHOD_PC) return false;
   if (o->solver != LP_SOLVER_CHOLESKY && o->solver != LP_SOLVER_WOODBURY) return false;
   if (o->reserved != 0 || o->reserved2 != 0) return false;
-  if (o->batch_tile != 0 && o->batch_tile != 32 && o->batch_tile != 64) return false;
+  if (o->batch_tile != 0 && o->batch_tile != 32 && o->batch_tile != 64 && o->batch_tile != 128)
+    return false;
   if (o->batch_graph_iters < 0 || o->batch_graph_iters > 16) return false;
   if (o->solver == LP_SOLVER_WOODBURY &&
       (o->precision != LP_PREC_FP64 || o->method != LP_METHOD_AFFINE || o->tape_capacity != 0))

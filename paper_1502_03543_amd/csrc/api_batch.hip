@@ -286,7 +286,8 @@ lp_status lp_batch_workspace_size(int32_t count, const int64_t* m, const int64_t
        !(o.mixed_switch_gap >= 0) || o.tape_capacity != 0))
     return LP_ERR_INVALID_ARG;
   if (o.solver != LP_SOLVER_CHOLESKY || o.reserved != 0 || o.reserved2 != 0) return LP_ERR_INVALID_ARG;
-  if (o.batch_tile != 0 && o.batch_tile != 32 && o.batch_tile != 64) return LP_ERR_INVALID_ARG;
+  if (o.batch_tile != 0 && o.batch_tile != 32 && o.batch_tile != 64 && o.batch_tile != 128)
+    return LP_ERR_INVALID_ARG;
   if (o.batch_graph_iters < 0 || o.batch_graph_iters > 16) return LP_ERR_INVALID_ARG;
   lp_batch h;
   h.count = count;

@@ -7,8 +7,9 @@
 // captures it once into a hipGraph and replays it:
 //   k_bbegin        per LP: stop tests, tape row, d = x/s, w = d o r_d
 //   k_brhs          per LP and row group: rhs = b + A w (wavefront per row)
-//   k_bsyrk_normal  per LP and lower 64-tile: M = A D A^T on the FP64 matrix
-//                   cores (the single-LP tile routine)
+//   k_bsyrk_normal16 per LP and lower 32- or 64-tile: M = A D A^T on the
+//                   FP64 matrix cores (16 x 16 x 4 blocks, an LP's tiles on
+//                   one XCD); 128-tiles run the stream-K tile routine
 //   per panel p:    k_bpotrf_panel (the single-LP panel routine), then
 //                   k_bsyrk_trailing (the tile routine in subtract mode);
 //                   k_bdiag_to_m puts the diagonal blocks into M at the end

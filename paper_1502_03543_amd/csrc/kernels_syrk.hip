@@ -6,8 +6,10 @@
 //   * k_syrk_sk (below): stream-K over 128 x 128 lower tiles on
 //     v_mfma_f64_16x16x4f64, the choice for large shapes;
 //   * k_syrk_f64: split-K over 64 or 128 lower tiles with the four-block
-//     v_mfma_f64_4x4x4f64 tile routine of syrk_tile.h (small shapes, the
-//     batched normal matrices and the Cholesky updates).
+//     v_mfma_f64_4x4x4f64 tile routine of syrk_tile.h (small shapes and the
+//     Cholesky updates);
+//   * k_bsyrk_normal16 / k_bsyrk_normal_sk: the batched normal matrices,
+//     one LP per workgroup row of tiles, on the 16x16x4 form.
 // Split-K writes per-split partial tiles; the last split of a tile to finish
 // (an arrival counter per tile) sums them in split order, so results do not
 // depend on scheduling.  The FP32 kernel (mixed precision) is further down.
@@ -205,28 +207,6 @@ __global__ __launch_bounds__(256) void k_syrk_reduce_f32(int mm, float* __restri
 constexpr int kKC128 = 32;  // K per stage of the 128 x 128 tile kernel
 constexpr int kKC64 = 32;   // and of the 64 x 64 one
 
-// Batched normal matrices: LP = blockIdx.y, lower BM-tile blockIdx.x of
-// M_i = A_i diag(d_i) A_i^T (rows of A_i need not be 16-byte aligned).
-// BM = 64 (2 x 2 wavefronts of 32 x 32) or 32 (of 16 x 16): the smaller
-// tile wastes less on small LPs and gives more workgroups per LP.
-template <int BM>
-__global__ __launch_bounds__(256) void k_bsyrk_normal(const BatchLP* __restrict__ lps,
-                                                       const int* __restrict__ go,
-                                                       const double* __restrict__ A,
-                                                       const double* __restrict__ d,
-                                                       double* __restrict__ Mpool) {
-  const int lp = blockIdx.y;
-  if (!go[lp]) return;
-  const BatchLP P = lps[lp];
-  const int nt = (P.m + BM - 1) / BM, ntiles = nt * (nt + 1) / 2;
-  const int t = blockIdx.x;
-  if (t >= ntiles) return;
-  __shared__ double2 lds2[syrk_tile_lds2<BM / 8, 32>()];
-  syrk_f64_tile<BM / 8, BM / 32, 32, true, false>(P.m, P.n, A + P.a_off, P.n, d + P.vn,
-                                                  Mpool + P.M_off, P.ldm, 0, t, ntiles, 0, 1, P.n,
-                                                  nullptr, lds2);
-}
-
 // Batched Cholesky trailing update after the panel at column p:
 // M22 -= L21 L21^T on the lower BM-tiles of each LP that has rows below p + 64.
 template <int BM>
@@ -331,7 +311,9 @@ struct SkShape {
 constexpr int kSkWC = 4;
 
 // Tile t over k in [kbeg, kend) into acc (the whole workgroup takes part).
-template <int WC>
+// VEC: 16-byte loads (rows of X and w 16-byte aligned, k range even);
+// otherwise element loads, any alignment and length.
+template <int WC, bool VEC = true>
 __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, long ldx,
                                         const double* __restrict__ w, int t, int kbeg, int kend,
                                         sk4 (&acc)[kSkT][SkShape<WC>::TC], bool active) {
@@ -354,10 +336,22 @@ __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, lo
       const int p = tid + NT * it;
       const int row = p / PPR, k = kb + 2 * (p % PPR);
       const long ra = min(row0 + row, mm - 1), rb = min(col0 + row, mm - 1);
-      const int kc = min(k, kend - 2);
-      pa[it] = *reinterpret_cast<const double2*>(X + ra * ldx + kc);
-      pb[it] = *reinterpret_cast<const double2*>(X + rb * ldx + kc);
-      pw[it] = *reinterpret_cast<const double2*>(w + kc);
+      if (VEC) {
+        const int kc = min(k, kend - 2);
+        pa[it] = *reinterpret_cast<const double2*>(X + ra * ldx + kc);
+        pb[it] = *reinterpret_cast<const double2*>(X + rb * ldx + kc);
+        pw[it] = *reinterpret_cast<const double2*>(w + kc);
+      } else {
+        // each element from its own column (clamped into the row; entries
+        // beyond kend are zeroed when staged)
+        const int k0 = min(k, kend - 1), k1 = min(k + 1, kend - 1);
+        pa[it].x = X[ra * ldx + k0];
+        pa[it].y = X[ra * ldx + k1];
+        pb[it].x = X[rb * ldx + k0];
+        pb[it].y = X[rb * ldx + k1];
+        pw[it].x = w[k0];
+        pw[it].y = w[k1];
+      }
     }
   };
   auto sstore = [&](int buf, int st) {
@@ -405,6 +399,170 @@ __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, lo
     if (st + 1 < nst) sstore(cur ^ 1, st + 1);
     __syncthreads();
   }
+}
+
+// Batched normal matrices on the stream-K tile routine: LP = blockIdx.y,
+// lower 128-tile blockIdx.x of M_i = A_i diag(d_i) A_i^T over the whole sum
+// (no split).  A tile reads each of its two 128-row panels of A_i once, so
+// an LP with m <= 128 reads its A once per operand and one with m <= 256
+// three times, against nine times with 32-row tiles; element loads, since
+// the rows of A_i need not be aligned or of even length.
+__global__ __launch_bounds__(SkShape<kSkWC>::threads) void k_bsyrk_normal_sk(
+    const BatchLP* __restrict__ lps, const int* __restrict__ go, const double* __restrict__ A,
+    const double* __restrict__ d, double* __restrict__ Mpool) {
+  constexpr int TC = SkShape<kSkWC>::TC;
+  const int lp = blockIdx.y;
+  if (!go[lp]) return;
+  const BatchLP P = lps[lp];
+  const int nt = (P.m + kSkBM - 1) / kSkBM, ntiles = nt * (nt + 1) / 2;
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int row0 = ti * kSkBM, col0 = tj * kSkBM;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr0 = (wv / kSkWC) * (16 * kSkT), wc0 = (wv % kSkWC) * (16 * TC);
+  const bool active = !(ti == tj && wr0 + 16 * kSkT <= wc0);
+  sk4 acc[kSkT][TC];
+#pragma unroll
+  for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+    for (int c = 0; c < TC; ++c) acc[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
+  sk_tile<kSkWC, false>(P.m, A + P.a_off, P.n, d + P.vn, t, 0, P.n, acc, active);
+  if (!active) return;
+  double* C = Mpool + P.M_off;
+#pragma unroll
+  for (int r = 0; r < kSkT; ++r)
+#pragma unroll
+    for (int c = 0; c < TC; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
+        if (gr < P.m && gc <= gr) C[(long)gr * P.ldm + gc] = acc[r][c][v];
+      }
+}
+
+// Batched normal matrices on v_mfma_f64_16x16x4f64 (lane layout as in the
+// stream-K routine above): lower BM-tile t of M_i = A_i diag(d_i) A_i^T over
+// the whole sum, 2 x 2 wavefronts of (BM/2) x (BM/2), stages of KC along K
+// through double-buffered LDS rows padded by two doubles.  BM = 32 (one
+// 16 x 16 block per wavefront) or 64 (2 x 2 blocks); element loads, since
+// the rows of A_i need not be aligned or of even length.  One-dimensional
+// grid of T x count8 workgroups (T = lower tiles of the largest LP, count8
+// = count rounded up to 8): workgroup b runs on XCD b % 8 and takes LP
+// 8 (j / T) + b % 8, tile j % T with j = b / 8, so all tiles of an LP share
+// one XCD's L2 and start together; they read the LP's A from that cache
+// after its first pass.
+template <int BM, int KC>
+__global__ __launch_bounds__(256) void k_bsyrk_normal16(const BatchLP* __restrict__ lps,
+                                                         const int* __restrict__ go,
+                                                         const double* __restrict__ A,
+                                                         const double* __restrict__ d,
+                                                         double* __restrict__ Mpool, int count,
+                                                         int T) {
+  constexpr int TB = BM / 32;             // 16 x 16 blocks per wavefront edge
+  constexpr int LS = KC + 2;              // padded LDS row length
+  constexpr int PPR = KC / 2;             // element pairs per row per stage
+  constexpr int PAIRS = BM * PPR / 256;   // pairs per thread per operand
+  static_assert(PAIRS >= 1 && BM * PPR % 256 == 0, "stage shape");
+  __shared__ __attribute__((aligned(16))) double lds[2][2][BM * LS];
+  const int b = blockIdx.x, j = b >> 3;
+  const int lp = (j / T) * 8 + (b & 7), t = j % T;
+  if (lp >= count || !go[lp]) return;
+  const BatchLP P = lps[lp];
+  const int mm = P.m, K = P.n;
+  const int nt = (mm + BM - 1) / BM;
+  if (t >= nt * (nt + 1) / 2) return;
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int row0 = ti * BM, col0 = tj * BM;
+  const double* __restrict__ X = A + P.a_off;
+  const double* __restrict__ w = d + P.vn;
+  const int nst = (K + KC - 1) / KC;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr0 = (wv >> 1) * (BM / 2), wc0 = (wv & 1) * (BM / 2);
+  // the wavefront of a diagonal tile that lies wholly above the diagonal idles
+  const bool active = !(ti == tj && wr0 + BM / 2 <= wc0);
+  sk4 acc[TB][TB];
+#pragma unroll
+  for (int r = 0; r < TB; ++r)
+#pragma unroll
+    for (int c = 0; c < TB; ++c) acc[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
+  double2 pa[PAIRS], pb[PAIRS], pw[PAIRS];
+  auto gload = [&](int st) {
+    const int kb = st * KC;
+#pragma unroll
+    for (int it = 0; it < PAIRS; ++it) {
+      const int p = tid + 256 * it;
+      const int row = p / PPR, k = kb + 2 * (p % PPR);
+      const long ra = min(row0 + row, mm - 1), rb = min(col0 + row, mm - 1);
+      const int k0 = min(k, K - 1), k1 = min(k + 1, K - 1);
+      pa[it].x = X[ra * K + k0];
+      pa[it].y = X[ra * K + k1];
+      pb[it].x = X[rb * K + k0];
+      pb[it].y = X[rb * K + k1];
+      pw[it].x = w[k0];
+      pw[it].y = w[k1];
+    }
+  };
+  auto sstore = [&](int buf, int st) {
+    const int kb = st * KC;
+#pragma unroll
+    for (int it = 0; it < PAIRS; ++it) {
+      const int p = tid + 256 * it;
+      const int row = p / PPR, kk = 2 * (p % PPR), k = kb + kk;
+      const bool va = row0 + row < mm, vb = col0 + row < mm;
+      const bool v0 = k < K, v1 = k + 1 < K;
+      double2 sa, sb;
+      sa.x = (va && v0) ? pa[it].x * pw[it].x : 0.0;
+      sa.y = (va && v1) ? pa[it].y * pw[it].y : 0.0;
+      sb.x = (vb && v0) ? pb[it].x : 0.0;
+      sb.y = (vb && v1) ? pb[it].y : 0.0;
+      *reinterpret_cast<double2*>(&lds[buf][0][row * LS + kk]) = sa;
+      *reinterpret_cast<double2*>(&lds[buf][1][row * LS + kk]) = sb;
+    }
+  };
+  if (nst > 0) {
+    gload(0);
+    sstore(0, 0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) gload(st + 1);
+    if (active) {
+      const double* la = lds[cur][0];
+      const double* lb = lds[cur][1];
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        double a[TB], bb[TB];
+#pragma unroll
+        for (int r = 0; r < TB; ++r) a[r] = la[(wr0 + 16 * r + li) * LS + 4 * ks + lk];
+#pragma unroll
+        for (int c = 0; c < TB; ++c) bb[c] = lb[(wc0 + 16 * c + li) * LS + 4 * ks + lk];
+#pragma unroll
+        for (int r = 0; r < TB; ++r)
+#pragma unroll
+          for (int c = 0; c < TB; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], bb[c], acc[r][c], 0, 0, 0);
+      }
+    }
+    if (st + 1 < nst) sstore(cur ^ 1, st + 1);
+    __syncthreads();
+  }
+  if (!active) return;
+  double* C = Mpool + P.M_off;
+#pragma unroll
+  for (int r = 0; r < TB; ++r)
+#pragma unroll
+    for (int c = 0; c < TB; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
+        if (gr < mm && gc <= gr) C[(long)gr * P.ldm + gc] = acc[r][c][v];
+      }
 }
 
 // C (lower, ldc) = X diag(w) X^T; X rows 16-byte aligned, K even.
@@ -694,18 +852,26 @@ bool launch_syrk_f32(hipStream_t st, int mm, int K, const float* X, long ldx, co
 void launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                          const int* go, const double* A, const double* d, double* Mpool) {
   const int nt = cdiv(max_m, tile);
-  if (tile == 32)
-    hipLaunchKernelGGL(k_bsyrk_normal<32>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st, lps,
-                       go, A, d, Mpool);
-  else
-    hipLaunchKernelGGL(k_bsyrk_normal<64>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st, lps,
-                       go, A, d, Mpool);
+  if (tile == 128)
+    hipLaunchKernelGGL(k_bsyrk_normal_sk, dim3(nt * (nt + 1) / 2, count),
+                       dim3(SkShape<kSkWC>::threads), 0, st, lps, go, A, d, Mpool);
+  else {
+    const int T = nt * (nt + 1) / 2;
+    const dim3 grid(T * 8 * cdiv(count, 8));
+    if (tile == 32)
+      hipLaunchKernelGGL((k_bsyrk_normal16<32, 32>), grid, dim3(256), 0, st, lps, go, A, d, Mpool,
+                         count, T);
+    else
+      hipLaunchKernelGGL((k_bsyrk_normal16<64, 16>), grid, dim3(256), 0, st, lps, go, A, d, Mpool,
+                         count, T);
+  }
 }
 
 void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                            const int* go, double* Mpool, int p) {
   const int mm = max_m - p - 64;
   if (mm <= 0) return;
+  if (tile > 64) tile = 64;  // the K = 64 updates keep 64-row tiles
   const int nt = cdiv(mm, tile);
   if (tile == 32)
     hipLaunchKernelGGL(k_bsyrk_trailing<32>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
@@ -717,6 +883,7 @@ void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const
 
 void launch_bsyrk_normal_f32(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                              const int* go, const float* A32, const float* sd32, float* M32) {
+  if (tile > 64) tile = 64;
   const int nt = cdiv(max_m, tile);
   if (tile == 32)
     hipLaunchKernelGGL(k_bsyrk_normal_f32<1>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
@@ -730,6 +897,7 @@ void launch_bsyrk_trailing_f32(hipStream_t st, int count, int max_m, int tile,
                                const BatchLP* lps, const int* go, float* M32, int p) {
   const int mm = max_m - p - 64;
   if (mm <= 0) return;
+  if (tile > 64) tile = 64;
   const int nt = cdiv(mm, tile);
   if (tile == 32)
     hipLaunchKernelGGL(k_bsyrk_trailing_f32<1>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,

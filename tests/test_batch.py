@@ -32,9 +32,9 @@ def _oracle_check(lp, status, iters, x, y, s, strict_iters=True):
         assert x @ s < 1e-8 and np.all(x > 0) and np.all(s > 0)
 
 
-@pytest.mark.parametrize("tile,giters", [(0, 0), (32, 1), (64, 8), (32, 3)])
+@pytest.mark.parametrize("tile,giters", [(0, 0), (32, 1), (64, 8), (32, 3), (128, 4)])
 def test_batch_small_matches_oracle(torch_dev, tile, giters):
-    """Every launch choice the autotuner may pick (tile edge 32 or 64,
+    """Every launch choice the autotuner may pick (tile edge 32, 64 or 128,
     iterations per captured graph) against the oracle, LP by LP."""
     from paper_1502_03543_amd import solver
     lps = lpgen.gen_batch(24, first_seed=100)

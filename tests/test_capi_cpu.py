@@ -135,7 +135,7 @@ def test_csr_validation():
 
 
 def test_batch_launch_options():
-    """lp_options.batch_tile (0, 32, 64) and batch_graph_iters (0..16) are
+    """lp_options.batch_tile (0, 32, 64, 128) and batch_graph_iters (0..16) are
     validated by the single-LP and the batched workspace calls alike."""
     o = capi.lp_options()
     capi.lp_options_default(C.byref(o))
@@ -144,7 +144,8 @@ def test_batch_launch_options():
     m = (C.c_int64 * 2)(16, 20)
     n = (C.c_int64 * 2)(40, 60)
     for tile, g, ok in ((32, 1, True), (64, 16, True), (0, 0, True), (16, 0, False),
-                        (128, 0, False), (32, 17, False), (32, -1, False)):
+                        (128, 4, True), (256, 0, False), (96, 0, False), (32, 17, False),
+                        (32, -1, False)):
         o.batch_tile, o.batch_graph_iters = tile, g
         want = capi.LP_OK if ok else capi.LP_ERR_INVALID_ARG
         assert capi.lp_batch_workspace_size(2, m, n, C.byref(o), C.byref(sz)) == want, (tile, g)
