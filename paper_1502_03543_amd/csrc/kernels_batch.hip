@@ -6,10 +6,12 @@
 // grids depend only on the batch (count, largest m and n), so the host
 // captures it once into a hipGraph and replays it:
 //   k_bbegin        per LP: stop tests, tape row, d = x/s, w = d o r_d
-//   k_brhs          per LP and row group: rhs = b + A w (wavefront per row)
 //   k_bsyrk_normal16 per LP and lower 32- or 64-tile: M = A D A^T on the
 //                   FP64 matrix cores (16 x 16 x 4 blocks, an LP's tiles on
-//                   one XCD); 128-tiles run the stream-K tile routine
+//                   one XCD); its diagonal tiles also form rhs = b + A w.
+//                   128-tiles run the stream-K tile routine, and k_brhs
+//                   (wavefront per row) forms rhs beside them and in the
+//                   mixed-precision iterations
 //   per panel p:    k_bpotrf_panel (the single-LP panel routine), then
 //                   k_bsyrk_trailing (the tile routine in subtract mode);
 //                   k_bdiag_to_m puts the diagonal blocks into M at the end
@@ -936,17 +938,22 @@ void launch_batch_step(hipStream_t st, const BatchArgs& a, int max_m, int k,
   int* err = adj ? adj->err : nullptr;
   if (k < 0) hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, st, a.active);
   hipLaunchKernelGGL(k_bbegin, dim3(count), dim3(256), 0, st, a, k);
-  hipLaunchKernelGGL(k_brhs, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a);
   // the FP64 factor: every stepping LP, or in a mixed-precision forward
-  // iteration the LPs that do not (or no longer) use the FP32 factor
+  // iteration the LPs that do not (or no longer) use the FP32 factor; the
+  // normal-matrix launch forms rhs too where it covers every stepping LP
   BatchArgs a64 = a;
   int* go_main = nullptr;
   if (a.mixed && k < 0) {
+    hipLaunchKernelGGL(k_brhs, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a);
     launch_bmix_factor(st, a, max_m);
     a64.go = a.go64;
     go_main = a.go;
+    launch_bsyrk_normal(st, count, max_m, a.tile, a.lps, a64.go, a.A, a.d, a.M, nullptr, nullptr,
+                        nullptr);
+  } else if (!launch_bsyrk_normal(st, count, max_m, a.tile, a.lps, a.go, a.A, a.d, a.M, a.w, a.b,
+                                  a.rhs)) {
+    hipLaunchKernelGGL(k_brhs, dim3(cdiv(max_m, 4), count), dim3(256), 0, st, a);
   }
-  launch_bsyrk_normal(st, count, max_m, a.tile, a.lps, a64.go, a.A, a.d, a.M);
   for (int p = 0; p < max_m; p += BT) {
     launch_bpotrf_panel(st, count, max_m, a.lps, a64.go, a.M, a.diag, p, a.fail, a.minp);
     launch_bsyrk_trailing(st, count, max_m, a.tile, a.lps, a64.go, a.M, p);

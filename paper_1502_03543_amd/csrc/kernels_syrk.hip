@@ -454,13 +454,17 @@ __global__ __launch_bounds__(SkShape<kSkWC>::threads) void k_bsyrk_normal_sk(
 // 8 (j / T) + b % 8, tile j % T with j = b / 8, so all tiles of an LP share
 // one XCD's L2 and start together; they read the LP's A from that cache
 // after its first pass.
-template <int BM, int KC>
-__global__ __launch_bounds__(256) void k_bsyrk_normal16(const BatchLP* __restrict__ lps,
-                                                         const int* __restrict__ go,
-                                                         const double* __restrict__ A,
-                                                         const double* __restrict__ d,
-                                                         double* __restrict__ Mpool, int count,
-                                                         int T) {
+// RHS: the diagonal tiles, which stage every row of A_i over the whole sum,
+// also form the right-hand side rhs_i = b_i + A_i w_i of their rows (w_i the
+// LP's d o r_d): each thread accumulates its staged elements times w in
+// stage order, then the 16 threads of a row add their sums in a fixed
+// butterfly order.
+template <int BM, int KC, bool RHS>
+__global__ __launch_bounds__(256) void k_bsyrk_normal16(
+    const BatchLP* __restrict__ lps, const int* __restrict__ go, const double* __restrict__ A,
+    const double* __restrict__ d, double* __restrict__ Mpool, int count, int T,
+    const double* __restrict__ wpool, const double* __restrict__ bpool,
+    double* __restrict__ rhspool) {
   constexpr int TB = BM / 32;             // 16 x 16 blocks per wavefront edge
   constexpr int LS = KC + 2;              // padded LDS row length
   constexpr int PPR = KC / 2;             // element pairs per row per stage
@@ -485,12 +489,17 @@ __global__ __launch_bounds__(256) void k_bsyrk_normal16(const BatchLP* __restric
   const int wr0 = (wv >> 1) * (BM / 2), wc0 = (wv & 1) * (BM / 2);
   // the wavefront of a diagonal tile that lies wholly above the diagonal idles
   const bool active = !(ti == tj && wr0 + BM / 2 <= wc0);
+  const bool diag = RHS && ti == tj;
+  const double* __restrict__ wr = wpool + P.vn;
   sk4 acc[TB][TB];
 #pragma unroll
   for (int r = 0; r < TB; ++r)
 #pragma unroll
     for (int c = 0; c < TB; ++c) acc[r][c] = sk4{0.0, 0.0, 0.0, 0.0};
-  double2 pa[PAIRS], pb[PAIRS], pw[PAIRS];
+  double2 pa[PAIRS], pb[PAIRS], pw[PAIRS], pr[PAIRS];
+  double racc[PAIRS];
+#pragma unroll
+  for (int it = 0; it < PAIRS; ++it) racc[it] = 0.0;
   auto gload = [&](int st) {
     const int kb = st * KC;
 #pragma unroll
@@ -505,6 +514,10 @@ __global__ __launch_bounds__(256) void k_bsyrk_normal16(const BatchLP* __restric
       pb[it].y = X[rb * K + k1];
       pw[it].x = w[k0];
       pw[it].y = w[k1];
+      if (diag) {
+        pr[it].x = wr[k0];
+        pr[it].y = wr[k1];
+      }
     }
   };
   auto sstore = [&](int buf, int st) {
@@ -515,6 +528,10 @@ __global__ __launch_bounds__(256) void k_bsyrk_normal16(const BatchLP* __restric
       const int row = p / PPR, kk = 2 * (p % PPR), k = kb + kk;
       const bool va = row0 + row < mm, vb = col0 + row < mm;
       const bool v0 = k < K, v1 = k + 1 < K;
+      if (diag) {
+        racc[it] = fma(v0 ? pa[it].x : 0.0, pr[it].x, racc[it]);
+        racc[it] = fma(v1 ? pa[it].y : 0.0, pr[it].y, racc[it]);
+      }
       double2 sa, sb;
       sa.x = (va && v0) ? pa[it].x * pw[it].x : 0.0;
       sa.y = (va && v1) ? pa[it].y * pw[it].y : 0.0;
@@ -551,6 +568,17 @@ __global__ __launch_bounds__(256) void k_bsyrk_normal16(const BatchLP* __restric
     }
     if (st + 1 < nst) sstore(cur ^ 1, st + 1);
     __syncthreads();
+  }
+  if (diag) {
+    // the PPR = 16 threads of a row are 16 aligned consecutive lanes
+#pragma unroll
+    for (int it = 0; it < PAIRS; ++it) {
+      double v = racc[it];
+#pragma unroll
+      for (int o = PPR / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+      const int p = tid + 256 * it, gr = row0 + p / PPR;
+      if (p % PPR == 0 && gr < mm) rhspool[P.vm + gr] = bpool[P.vm + gr] + v;
+    }
   }
   if (!active) return;
   double* C = Mpool + P.M_off;
@@ -849,22 +877,33 @@ bool launch_syrk_f32(hipStream_t st, int mm, int K, const float* X, long ldx, co
   return true;
 }
 
-void launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
-                         const int* go, const double* A, const double* d, double* Mpool) {
+bool launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
+                         const int* go, const double* A, const double* d, double* Mpool,
+                         const double* w, const double* b, double* rhs) {
   const int nt = cdiv(max_m, tile);
-  if (tile == 128)
+  if (tile == 128) {
     hipLaunchKernelGGL(k_bsyrk_normal_sk, dim3(nt * (nt + 1) / 2, count),
                        dim3(SkShape<kSkWC>::threads), 0, st, lps, go, A, d, Mpool);
-  else {
-    const int T = nt * (nt + 1) / 2;
-    const dim3 grid(T * 8 * cdiv(count, 8));
-    if (tile == 32)
-      hipLaunchKernelGGL((k_bsyrk_normal16<32, 32>), grid, dim3(256), 0, st, lps, go, A, d, Mpool,
-                         count, T);
-    else
-      hipLaunchKernelGGL((k_bsyrk_normal16<64, 16>), grid, dim3(256), 0, st, lps, go, A, d, Mpool,
-                         count, T);
+    return false;
   }
+  const int T = nt * (nt + 1) / 2;
+  const dim3 grid(T * 8 * cdiv(count, 8));
+  if (rhs) {
+    if (tile == 32)
+      hipLaunchKernelGGL((k_bsyrk_normal16<32, 32, true>), grid, dim3(256), 0, st, lps, go, A, d,
+                         Mpool, count, T, w, b, rhs);
+    else
+      hipLaunchKernelGGL((k_bsyrk_normal16<64, 16, true>), grid, dim3(256), 0, st, lps, go, A, d,
+                         Mpool, count, T, w, b, rhs);
+    return true;
+  }
+  if (tile == 32)
+    hipLaunchKernelGGL((k_bsyrk_normal16<32, 32, false>), grid, dim3(256), 0, st, lps, go, A, d,
+                       Mpool, count, T, w, b, rhs);
+  else
+    hipLaunchKernelGGL((k_bsyrk_normal16<64, 16, false>), grid, dim3(256), 0, st, lps, go, A, d,
+                       Mpool, count, T, w, b, rhs);
+  return false;
 }
 
 void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,

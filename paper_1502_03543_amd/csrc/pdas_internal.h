@@ -247,7 +247,7 @@ struct BatchArgs {
   unsigned long long* minp;  // per LP: smallest pivot (bit pattern of a positive double)
   double* psi;          // per LP: psi of the current direction
   long long* arg;       // per LP: its first maximiser (x block j, s block n + j)
-  int tile;             // edge of the normal-matrix and trailing-update tiles (32, 64)
+  int tile;             // edge of the normal-matrix tiles (32, 64, 128; updates: 32, 64)
   int nslice;           // 256-column slices of the widest LP
   double* dpv;          // per LP and slice: the slice's ratio-test maximum,
   long long* dpi;       //   its first maximiser
@@ -308,9 +308,12 @@ void launch_bpotrf_panel_f32(hipStream_t st, int count, int max_m, const BatchLP
                              unsigned long long* minp_bits);
 void launch_bdiag_to_m_f32(hipStream_t st, int count, int max_m, const BatchLP* lps,
                            const int* go, float* M32, const float* diag32);
-// tile: 32 or 64 (the edge of the lower tiles)
-void launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
-                         const int* go, const double* A, const double* d, double* Mpool);
+// tile: 32, 64 or 128 (the edge of the lower tiles).  With rhs given, the
+// 32- and 64-tile kernels also form rhs_i = b_i + A_i w_i and the call
+// returns true; otherwise (and always for 128) rhs is the caller's to form.
+bool launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
+                         const int* go, const double* A, const double* d, double* Mpool,
+                         const double* w, const double* b, double* rhs);
 void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                            const int* go, double* Mpool, int p);
 void launch_bpotrf_panel(hipStream_t st, int count, int max_m, const BatchLP* lps, const int* go,
