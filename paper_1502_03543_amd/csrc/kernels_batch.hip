@@ -99,13 +99,32 @@ __device__ void wg_trsv_fwd(int m, const double* L, long ld, const double* r, do
     } else if (wv > 0) {
       diag_store(Ld, tid, pre);
     }
-    // wave wv: rows wv, wv+4, ...; lanes over columns 0..i0-1
-    for (int ii = wv; ii < BT; ii += 4) {
-      double acc = 0.0;
-      if (ii < rows)
-        for (int c = lane; c < i0; c += 64) acc += L[(long)(i0 + ii) * ld + c] * out[c];
-      acc = wsum(acc);
-      if (lane == 0) sacc[ii] = acc;
+    // wave wv: rows 16 wv .. 16 wv + 15, lanes over columns 0..i0-1; the
+    // sixteen rows' loads of a column group are issued together
+    {
+      constexpr int RPW = BT / 4;
+      const double* Lw = L + (long)(i0 + RPW * wv) * ld;
+      const int nr = min(RPW, rows - RPW * wv);
+      double acc[RPW];
+#pragma unroll
+      for (int q = 0; q < RPW; ++q) acc[q] = 0.0;
+      if (nr > 0) {
+        // rows past the last are read as the last row (in the matrix, so
+        // every load is issued without a branch) and weighted by zero
+        for (int c = lane; c < i0; c += 64) {
+          const double oc = out[c];
+          double lv[RPW];
+#pragma unroll
+          for (int q = 0; q < RPW; ++q) lv[q] = Lw[(long)min(q, nr - 1) * ld + c];
+#pragma unroll
+          for (int q = 0; q < RPW; ++q) acc[q] += lv[q] * (q < nr ? oc : 0.0);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RPW; ++q) {
+        const double v = wsum(acc[q]);
+        if (lane == 0) sacc[RPW * wv + q] = v;
+      }
     }
     __syncthreads();
     // wavefronts 1..3 load the next diagonal block while wavefront 0 solves
