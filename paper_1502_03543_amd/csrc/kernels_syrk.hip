@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing_f32(const BatchLP* __res
 // keeps this kernel off the LDS bandwidth limit.
 //
 // Workgroup tile 128 x 128 (2 x 4 wavefronts of 64 x 32), stages of 32 along
-// K through double-buffered LDS rows padded to 34 doubles.  The iteration
+// K through double-buffered LDS rows padded to 33 doubles.  The iteration
 // space (lower tiles x stages, tile-major) is cut into kSkGroups equal
 // contiguous ranges, one per workgroup, so every compute unit gets the same
 // amount of matrix work whatever the number of tiles.  A range covers the
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_bsyrk_trailing_f32(const BatchLP* __res
 constexpr int kSkT = 4;                 // 16 x 16 blocks per wavefront, rows
 constexpr int kSkBM = 32 * kSkT;        // 128
 constexpr int kSkKC = 32;
-constexpr int kSkLS = kSkKC + 2;
+constexpr int kSkLS = kSkKC + 1;     // odd: the 16 rows of an operand read fall in distinct banks
 constexpr int kSkGroups = 256;          // one workgroup per compute unit
 
 typedef double sk4 __attribute__((ext_vector_type(4)));
@@ -367,8 +367,12 @@ __device__ __forceinline__ void sk_tile(int mm, const double* __restrict__ X, lo
       sa.y = (va && v1) ? pa[it].y * pw[it].y : 0.0;
       sb.x = (vb && v0) ? pb[it].x : 0.0;
       sb.y = (vb && v1) ? pb[it].y : 0.0;
-      *reinterpret_cast<double2*>(&lds[buf][0][row * kSkLS + kk]) = sa;
-      *reinterpret_cast<double2*>(&lds[buf][1][row * kSkLS + kk]) = sb;
+      double* da = &lds[buf][0][row * kSkLS + kk];
+      double* db = &lds[buf][1][row * kSkLS + kk];
+      da[0] = sa.x;
+      da[1] = sa.y;
+      db[0] = sb.x;
+      db[1] = sb.y;
     }
   };
   if (nst > 0) {
