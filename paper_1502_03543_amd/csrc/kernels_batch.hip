@@ -55,50 +55,64 @@ __device__ inline void amerge(double& v, long long& i, double v2, long long i2) 
   }
 }
 
-// The 64 x 64 diagonal block at (i0, i0) (rows < nr kept, identity beyond,
-// upper part zero) as staged in LDS, held by wavefronts 1..3 in registers:
-// element e = (tid - 64) + 192 q of the block, q < kPre.
-constexpr int kPre = (BT * BT + 191) / 192;
-__device__ inline void diag_load(const double* L, long ld, int i0, int nr, int tid,
-                                 double (&pre)[kPre]) {
-#pragma unroll
-  for (int q = 0; q < kPre; ++q) {
-    const int e = (tid - 64) + 192 * q;
-    const int ii = e / BT, k = e % BT;
-    double v = (ii == k) ? 1.0 : 0.0;
-    if (e < BT * BT && ii < nr && k <= ii) v = L[(long)(i0 + ii) * ld + i0 + k];
-    pre[q] = v;
-  }
-}
-__device__ inline void diag_store(double* Ld, int tid, const double (&pre)[kPre]) {
-#pragma unroll
-  for (int q = 0; q < kPre; ++q) {
-    const int e = (tid - 64) + 192 * q;
-    if (e < BT * BT) Ld[(e / BT) * (BT + 1) + e % BT] = pre[q];
-  }
+// The 64 x 64 diagonal block at (i0, i0) of L (rows < nr kept, identity
+// beyond, upper part zero) into an LDS block of row length BT + 1.
+// diag_first: by the whole workgroup; diag_next: by wavefronts 1..3 while
+// wavefront 0 solves the current block from the other LDS block.  Either
+// way all loads of a thread are issued before its first LDS store.
+constexpr int kLdBlk = BT * (BT + 1);
+
+// A zero the compiler cannot see through: index arithmetic offset by it is
+// redone at each use instead of being hoisted out of the block loop, where
+// its per-element values would stay live in registers across every block.
+__device__ inline int opaque_zero() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
 }
 
+template <int NT>
+__device__ __forceinline__ void diag_stage(const double* L, long ld, int i0, int nr, int t0,
+                                           double* Ld) {
+  constexpr int Q = (BT * BT + NT - 1) / NT;
+  const int t = t0 + opaque_zero();
+  double v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = t + NT * q, ii = e / BT, k = e % BT;
+    v[q] = (e < BT * BT && ii < nr && k <= ii) ? L[(long)(i0 + ii) * ld + i0 + k]
+                                                : ((ii == k) ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = t + NT * q;
+    if (e < BT * BT) Ld[(e / BT) * (BT + 1) + e % BT] = v[q];
+  }
+}
+__device__ __forceinline__ void diag_first(const double* L, long ld, int i0, int nr, int tid,
+                                           double* Ld) {
+  diag_stage<256>(L, ld, i0, nr, tid, Ld);
+}
+__device__ __forceinline__ void diag_next(const double* L, long ld, int i0, int nr, int tid,
+                                          double* Ld) {
+  diag_stage<192>(L, ld, i0, nr, tid - 64, Ld);
+}
+
+// LDS of the workgroup solves (doubles): partial sums, two diagonal blocks
+constexpr int kTrsvLds = 4 * BT + 2 * kLdBlk;
+
 // z = L^-1 r (forward) into out; L row-major lower with ld.  One workgroup:
-// per 64-row block, all threads form the off-diagonal product and stage the
-// diagonal block in LDS, then wave 0 solves it with readlane broadcasts.
-__device__ void wg_trsv_fwd(int m, const double* L, long ld, const double* r, double* out,
-                            double* lds) {
-  double* sacc = lds;           // [64]
-  double* Ld = lds + BT;        // [64][65]
+// per 64-row block, all threads form the off-diagonal product, then wave 0
+// solves the diagonal block (staged in LDS by the other waves during the
+// previous block's solve) with readlane broadcasts.
+__device__ __forceinline__ void wg_trsv_fwd(int m, const double* L, long ld, const double* r,
+                                            double* out, double* lds) {
+  double* sacc = lds;  // [64]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  double pre[kPre];
   for (int i0 = 0; i0 < m; i0 += BT) {
     const int rows = min(BT, m - i0);
-    if (i0 == 0) {
-      for (int e = tid; e < BT * BT; e += 256) {
-        const int ii = e / BT, k = e % BT;
-        double v = (ii == k) ? 1.0 : 0.0;
-        if (ii < rows && k <= ii) v = L[(long)(i0 + ii) * ld + i0 + k];
-        Ld[ii * (BT + 1) + k] = v;
-      }
-    } else if (wv > 0) {
-      diag_store(Ld, tid, pre);
-    }
+    double* Ld = lds + 4 * BT + ((i0 / BT) & 1) * kLdBlk;
+    if (i0 == 0) diag_first(L, ld, i0, rows, tid, Ld);
     // wave wv: rows 16 wv .. 16 wv + 15, lanes over columns 0..i0-1; the
     // sixteen rows' loads of a column group are issued together
     {
@@ -120,25 +134,44 @@ __device__ void wg_trsv_fwd(int m, const double* L, long ld, const double* r, do
           for (int q = 0; q < RPW; ++q) acc[q] += lv[q] * (q < nr ? oc : 0.0);
         }
       }
+      // the sixteen lane sums reduced together: each butterfly level hands
+      // half of the remaining rows to the partner lane, so after four
+      // levels lane l holds row (l / 4) % 16 summed over its 16 lanes, and
+      // two more levels finish the sums over all 64
 #pragma unroll
-      for (int q = 0; q < RPW; ++q) {
-        const double v = wsum(acc[q]);
-        if (lane == 0) sacc[RPW * wv + q] = v;
+      for (int h = RPW / 2, o = 32; h >= 1; h >>= 1, o >>= 1) {
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+          const double keep = up ? acc[q + h] : acc[q];
+          const double send = up ? acc[q] : acc[q + h];
+          acc[q] = keep + __shfl_xor(send, o, 64);
+        }
       }
+      double v = acc[0];
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 1, 64);
+      if ((lane & 3) == 0) sacc[RPW * wv + ((lane >> 2) & 15)] = v;
     }
     __syncthreads();
-    // wavefronts 1..3 load the next diagonal block while wavefront 0 solves
-    if (wv > 0 && i0 + BT < m) diag_load(L, ld, i0 + BT, min(BT, m - i0 - BT), tid, pre);
+    // wavefronts 1..3 stage the next diagonal block while wavefront 0 solves
+    if (wv > 0 && i0 + BT < m)
+      diag_next(L, ld, i0 + BT, min(BT, m - i0 - BT), tid, lds + 4 * BT + ((i0 / BT + 1) & 1) * kLdBlk);
     if (wv == 0) {
+      // each row scaled by its pivot's reciprocal, so that step j is one
+      // broadcast and one fused multiply-add: z_j is row j's value itself,
+      // and the scaled multipliers (zero where row i does not take step j)
+      // are formed beside the chain
       const double dl = 1.0 / Ld[lane * (BT + 1) + lane];
-      double val = (lane < rows) ? (r[i0 + lane] - sacc[lane]) : 0.0;
+      double val = ((lane < rows) ? (r[i0 + lane] - sacc[lane]) : 0.0) * dl;
       double mine = 0.0;
 #pragma unroll 4
       for (int j = 0; j < BT; ++j) {
-        const double lij = Ld[lane * (BT + 1) + j];
-        const double zj = rl(val, j) * rl(dl, j);
-        if (lane == j) mine = zj;
-        if (lane > j) val -= lij * zj;
+        // (read by every lane, zeroed through the scale: no branch)
+        const double lij = Ld[lane * (BT + 1) + j] * (lane > j ? dl : 0.0);
+        const double zj = rl(val, j);
+        mine = lane == j ? zj : mine;
+        val = fma(-lij, zj, val);
       }
       if (lane < rows) out[i0 + lane] = mine;
     }
@@ -147,25 +180,15 @@ __device__ void wg_trsv_fwd(int m, const double* L, long ld, const double* r, do
 }
 
 // y = L^-T z into out.
-__device__ void wg_trsv_bwd(int m, const double* L, long ld, const double* z, double* out,
-                            double* lds) {
-  double* sacc = lds;           // [4][64]
-  double* Ld = lds + 4 * BT;    // [64][65]
+__device__ __forceinline__ void wg_trsv_bwd(int m, const double* L, long ld, const double* z,
+                                            double* out, double* lds) {
+  double* sacc = lds;  // [4][64]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nblk = (m + BT - 1) / BT;
-  double pre[kPre];
   for (int rb = nblk - 1; rb >= 0; --rb) {
     const int c0 = rb * BT, cols = min(BT, m - c0);
-    if (rb == nblk - 1) {
-      for (int e = tid; e < BT * BT; e += 256) {
-        const int ii = e / BT, k = e % BT;
-        double v = (ii == k) ? 1.0 : 0.0;
-        if (ii < cols && k <= ii) v = L[(long)(c0 + ii) * ld + c0 + k];
-        Ld[ii * (BT + 1) + k] = v;
-      }
-    } else if (wv > 0) {
-      diag_store(Ld, tid, pre);
-    }
+    double* Ld = lds + 4 * BT + ((nblk - 1 - rb) & 1) * kLdBlk;
+    if (rb == nblk - 1) diag_first(L, ld, c0, cols, tid, Ld);
     double acc = 0.0;
     if (lane < cols) {
 #pragma unroll 8
@@ -173,19 +196,21 @@ __device__ void wg_trsv_bwd(int m, const double* L, long ld, const double* z, do
     }
     sacc[wv * BT + lane] = acc;
     __syncthreads();
-    // wavefronts 1..3 load the next diagonal block while wavefront 0 solves
-    if (wv > 0 && rb > 0) diag_load(L, ld, c0 - BT, BT, tid, pre);
+    // wavefronts 1..3 stage the next diagonal block while wavefront 0 solves
+    if (wv > 0 && rb > 0) diag_next(L, ld, c0 - BT, BT, tid, lds + 4 * BT + ((nblk - rb) & 1) * kLdBlk);
     if (wv == 0) {
+      // scaled as in the forward solve: one broadcast and one fused
+      // multiply-add per step
       const double dl = 1.0 / Ld[lane * (BT + 1) + lane];
       const double tot = ((sacc[lane] + sacc[BT + lane]) + sacc[2 * BT + lane]) + sacc[3 * BT + lane];
-      double val = (lane < cols) ? (z[c0 + lane] - tot) : 0.0;
+      double val = ((lane < cols) ? (z[c0 + lane] - tot) : 0.0) * dl;
       double mine = 0.0;
 #pragma unroll 4
       for (int j = BT - 1; j >= 0; --j) {
-        const double lji = Ld[j * (BT + 1) + lane];
-        const double yj = rl(val, j) * rl(dl, j);
-        if (lane == j) mine = yj;
-        if (lane < j) val -= lji * yj;
+        const double lji = Ld[j * (BT + 1) + lane] * (lane < j ? dl : 0.0);
+        const double yj = rl(val, j);
+        mine = lane == j ? yj : mine;
+        val = fma(-lji, yj, val);
       }
       if (lane < cols) out[c0 + lane] = mine;
     }
@@ -336,7 +361,7 @@ __global__ __launch_bounds__(256) void k_brhs(BatchArgs a) {
 // (go_main, when given, is the stepping flag to clear on a breakdown when
 // a.go is a narrower mask: the FP64 factor of a mixed-precision batch.)
 __global__ __launch_bounds__(256) void k_btrsv(BatchArgs a, int k, int* err, int* go_main) {
-  __shared__ double lds[4 * BT + BT * (BT + 1)];
+  __shared__ double lds[kTrsvLds];
   const int lp = blockIdx.x;
   if (!a.go[lp]) return;
   const BatchLP P = a.lps[lp];
@@ -620,7 +645,7 @@ __global__ __launch_bounds__(256) void k_badj_dyb(BatchArgs a, BatchAdj g) {
 
 // 3. lambda = M^-1 dybar with the recomputed factor (one workgroup per LP)
 __global__ __launch_bounds__(256) void k_badj_solve(BatchArgs a, BatchAdj g) {
-  __shared__ double lds[4 * BT + BT * (BT + 1)];
+  __shared__ double lds[kTrsvLds];
   const int lp = blockIdx.x;
   if (!a.go[lp]) return;
   const BatchLP P = a.lps[lp];
@@ -818,7 +843,7 @@ __global__ __launch_bounds__(256) void k_bmix_begin(BatchArgs a) {
 // After the FP32 factor: a failed pivot ends the FP32 attempt; otherwise L
 // is widened into the FP64 matrix and the first solve gives dy.
 __global__ __launch_bounds__(256) void k_bmix_solve0(BatchArgs a) {
-  __shared__ double lds[4 * BT + BT * (BT + 1)];
+  __shared__ double lds[kTrsvLds];
   const int lp = blockIdx.x;
   if (!a.m32[lp]) return;
   const BatchLP P = a.lps[lp];
@@ -878,7 +903,7 @@ __global__ __launch_bounds__(256) void k_bref_r(BatchArgs a) {
 
 // delta = L^-T L^-1 r, dy += delta, then the convergence test.
 __global__ __launch_bounds__(256) void k_bref_solve(BatchArgs a) {
-  __shared__ double lds[4 * BT + BT * (BT + 1)];
+  __shared__ double lds[kTrsvLds];
   const int lp = blockIdx.x;
   if (!a.refm[lp]) return;
   const BatchLP P = a.lps[lp];

@@ -61,10 +61,11 @@ def _build() -> str:
     jobs = []
     for name in SOURCES:
         text = open(os.path.join(CSRC, name + ".hip")).read()
-        if name == "kernels_chol":
+        if name in ("kernels_chol", "kernels_batch"):
             if ASM_ZERO not in text:
-                raise RuntimeError("kernels_chol.hip: opaque-zero asm not found")
+                raise RuntimeError(f"{name}.hip: opaque-zero asm not found")
             text = text.replace(ASM_ZERO, "z = 0;")
+        if name == "kernels_chol":
             if ASM_PIN not in text:
                 raise RuntimeError("kernels_chol.hip: register-pin asm not found")
             text = text.replace(ASM_PIN, "(void)v;")
