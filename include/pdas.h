@@ -129,7 +129,10 @@ typedef struct lp_options {
   int32_t method;          /* lp_method (default LP_METHOD_AFFINE)               */
   int32_t solver;          /* lp_solver (default LP_SOLVER_CHOLESKY)             */
   int32_t batch_tile;      /* lp_batch_*: normal-matrix and trailing-update tile
-                              edge, 0 (library's choice: 64), 32, 64 or 128
+                              edge, 0 (library's choice: FP64 normal matrix
+                              on 64-edge tiles for LPs with m > 128 and
+                              32-edge tiles for the others, trailing updates
+                              on 32, the FP32 path on 64), 32, 64 or 128
                               (128: FP64 normal matrix on 128 x 128 tiles of
                               eight wavefronts; trailing updates and the FP32
                               normal matrix then use 64); see

@@ -113,7 +113,7 @@ def tune(m: int, n: int, precision: str = "fp64", seed: int = 0, write: bool = T
 
 
 # batched solver: (batch_tile, batch_graph_iters)
-BATCH_CANDIDATES = [(t, g) for t in (64, 32, 128) for g in (1, 2, 4, 8)]
+BATCH_CANDIDATES = [(t, g) for t in (0, 64, 32, 128) for g in (1, 2, 4, 8)]
 
 
 def batch_signature(m, n) -> str:

@@ -341,7 +341,7 @@ lp_status lp_batch_setup(lp_batch** out, int32_t count, const int64_t* m, const 
   a.A = A_packed;
   a.lps = h->lps;
   a.state = h->state;
-  a.tile = h->opt.batch_tile ? h->opt.batch_tile : 64;
+  a.tile = h->opt.batch_tile;  // 0: per-LP tile edges (the launchers' choice)
   h->graph_iters = h->opt.batch_graph_iters ? h->opt.batch_graph_iters : kItersPerGraph;
   a.alpha = h->opt.alpha;
   for (int i = 0; i < count; ++i) {

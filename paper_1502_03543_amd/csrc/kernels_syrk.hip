@@ -13,6 +13,7 @@
 // Split-K writes per-split partial tiles; the last split of a tile to finish
 // (an arrival counter per tile) sums them in split order, so results do not
 // depend on scheduling.  The FP32 kernel (mixed precision) is further down.
+#include <algorithm>
 #include <cmath>
 
 #include "pdas_internal.h"
@@ -463,25 +464,27 @@ __global__ __launch_bounds__(SkShape<kSkWC>::threads) void k_bsyrk_normal_sk(
 // LP's d o r_d): each thread accumulates its staged elements times w in
 // stage order, then the 16 threads of a row add their sums in a fixed
 // butterfly order.
+template <int BM, int KC>
+constexpr int bsyrk16_lds_doubles() {
+  return 2 * 2 * BM * (KC + 2);
+}
+
+// Lower tile t of LP P (the whole workgroup; t below the LP's tile count).
 template <int BM, int KC, bool RHS>
-__global__ __launch_bounds__(256) void k_bsyrk_normal16(
-    const BatchLP* __restrict__ lps, const int* __restrict__ go, const double* __restrict__ A,
-    const double* __restrict__ d, double* __restrict__ Mpool, int count, int T,
-    const double* __restrict__ wpool, const double* __restrict__ bpool,
-    double* __restrict__ rhspool) {
+__device__ __forceinline__ void bsyrk16_tile(const BatchLP& P, int t,
+                                             const double* __restrict__ A,
+                                             const double* __restrict__ d,
+                                             double* __restrict__ Mpool,
+                                             const double* __restrict__ wpool,
+                                             const double* __restrict__ bpool,
+                                             double* __restrict__ rhspool, double* lds_base) {
   constexpr int TB = BM / 32;             // 16 x 16 blocks per wavefront edge
   constexpr int LS = KC + 2;              // padded LDS row length
   constexpr int PPR = KC / 2;             // element pairs per row per stage
   constexpr int PAIRS = BM * PPR / 256;   // pairs per thread per operand
   static_assert(PAIRS >= 1 && BM * PPR % 256 == 0, "stage shape");
-  __shared__ __attribute__((aligned(16))) double lds[2][2][BM * LS];
-  const int b = blockIdx.x, j = b >> 3;
-  const int lp = (j / T) * 8 + (b & 7), t = j % T;
-  if (lp >= count || !go[lp]) return;
-  const BatchLP P = lps[lp];
+  double(*lds)[2][BM * LS] = reinterpret_cast<double(*)[2][BM * LS]>(lds_base);
   const int mm = P.m, K = P.n;
-  const int nt = (mm + BM - 1) / BM;
-  if (t >= nt * (nt + 1) / 2) return;
   int ti, tj;
   tile_coords(t, ti, tj);
   const int row0 = ti * BM, col0 = tj * BM;
@@ -595,6 +598,47 @@ __global__ __launch_bounds__(256) void k_bsyrk_normal16(
         const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
         if (gr < mm && gc <= gr) C[(long)gr * P.ldm + gc] = acc[r][c][v];
       }
+}
+
+template <int BM, int KC, bool RHS>
+__global__ __launch_bounds__(256) void k_bsyrk_normal16(
+    const BatchLP* __restrict__ lps, const int* __restrict__ go, const double* __restrict__ A,
+    const double* __restrict__ d, double* __restrict__ Mpool, int count, int T,
+    const double* __restrict__ wpool, const double* __restrict__ bpool,
+    double* __restrict__ rhspool) {
+  __shared__ __attribute__((aligned(16))) double lds[bsyrk16_lds_doubles<BM, KC>()];
+  const int b = blockIdx.x, j = b >> 3;
+  const int lp = (j / T) * 8 + (b & 7), t = j % T;
+  if (lp >= count || !go[lp]) return;
+  const BatchLP P = lps[lp];
+  const int nt = (P.m + BM - 1) / BM;
+  if (t >= nt * (nt + 1) / 2) return;
+  bsyrk16_tile<BM, KC, RHS>(P, t, A, d, Mpool, wpool, bpool, rhspool, lds);
+}
+
+// Per-LP tile edge: 64 (intensity) for LPs with m > kBsyrkSmall, 32 (less
+// padding) for the others; with m at most 4 kBsyrkSmall an LP of either kind
+// has at most 10 lower tiles, so the grid (T tiles per LP, mapped to XCDs
+// as above) carries few idle workgroups.
+constexpr int kBsyrkSmall = 128;
+template <bool RHS>
+__global__ __launch_bounds__(256) void k_bsyrk_normal_hy(
+    const BatchLP* __restrict__ lps, const int* __restrict__ go, const double* __restrict__ A,
+    const double* __restrict__ d, double* __restrict__ Mpool, int count, int T,
+    const double* __restrict__ wpool, const double* __restrict__ bpool,
+    double* __restrict__ rhspool) {
+  constexpr int L32 = bsyrk16_lds_doubles<32, 32>(), L64 = bsyrk16_lds_doubles<64, 16>();
+  __shared__ __attribute__((aligned(16))) double lds[L32 > L64 ? L32 : L64];
+  const int b = blockIdx.x, j = b >> 3;
+  const int lp = (j / T) * 8 + (b & 7), t = j % T;
+  if (lp >= count || !go[lp]) return;
+  const BatchLP P = lps[lp];
+  const bool big = P.m > kBsyrkSmall;
+  const int bm = big ? 64 : 32;
+  const int nt = (P.m + bm - 1) / bm;
+  if (t >= nt * (nt + 1) / 2) return;
+  if (big) bsyrk16_tile<64, 16, RHS>(P, t, A, d, Mpool, wpool, bpool, rhspool, lds);
+  else bsyrk16_tile<32, 32, RHS>(P, t, A, d, Mpool, wpool, bpool, rhspool, lds);
 }
 
 // C (lower, ldc) = X diag(w) X^T; X rows 16-byte aligned, K even.
@@ -884,6 +928,18 @@ bool launch_syrk_f32(hipStream_t st, int mm, int K, const float* X, long ldx, co
 bool launch_bsyrk_normal(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                          const int* go, const double* A, const double* d, double* Mpool,
                          const double* w, const double* b, double* rhs) {
+  if (tile == 0) {
+    const int n64 = cdiv(max_m, 64), n32 = cdiv(std::min(max_m, kBsyrkSmall), 32);
+    const int T = std::max(n64 * (n64 + 1) / 2, n32 * (n32 + 1) / 2);
+    const dim3 grid(T * 8 * cdiv(count, 8));
+    if (rhs)
+      hipLaunchKernelGGL(k_bsyrk_normal_hy<true>, grid, dim3(256), 0, st, lps, go, A, d, Mpool,
+                         count, T, w, b, rhs);
+    else
+      hipLaunchKernelGGL(k_bsyrk_normal_hy<false>, grid, dim3(256), 0, st, lps, go, A, d, Mpool,
+                         count, T, w, b, rhs);
+    return rhs != nullptr;
+  }
   const int nt = cdiv(max_m, tile);
   if (tile == 128) {
     hipLaunchKernelGGL(k_bsyrk_normal_sk, dim3(nt * (nt + 1) / 2, count),
@@ -914,6 +970,7 @@ void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const
                            const int* go, double* Mpool, int p) {
   const int mm = max_m - p - 64;
   if (mm <= 0) return;
+  if (tile == 0) tile = 32;  // the library's choice beside per-LP normal-matrix tiles
   if (tile > 64) tile = 64;  // the K = 64 updates keep 64-row tiles
   const int nt = cdiv(mm, tile);
   if (tile == 32)
@@ -926,7 +983,7 @@ void launch_bsyrk_trailing(hipStream_t st, int count, int max_m, int tile, const
 
 void launch_bsyrk_normal_f32(hipStream_t st, int count, int max_m, int tile, const BatchLP* lps,
                              const int* go, const float* A32, const float* sd32, float* M32) {
-  if (tile > 64) tile = 64;
+  if (tile == 0 || tile > 64) tile = 64;
   const int nt = cdiv(max_m, tile);
   if (tile == 32)
     hipLaunchKernelGGL(k_bsyrk_normal_f32<1>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,
@@ -940,7 +997,7 @@ void launch_bsyrk_trailing_f32(hipStream_t st, int count, int max_m, int tile,
                                const BatchLP* lps, const int* go, float* M32, int p) {
   const int mm = max_m - p - 64;
   if (mm <= 0) return;
-  if (tile > 64) tile = 64;
+  if (tile == 0 || tile > 64) tile = 64;
   const int nt = cdiv(mm, tile);
   if (tile == 32)
     hipLaunchKernelGGL(k_bsyrk_trailing_f32<1>, dim3(nt * (nt + 1) / 2, count), dim3(256), 0, st,

@@ -106,8 +106,8 @@ def _lps():
 @pytest.mark.parametrize("tile", [0, 32, 128])
 def test_emulated_batch_matches_oracle(emu, tmp_path, tile):
     lps = _lps()
-    if tile == 128:
-        lps.append(lpgen.gen_lp(150, 331, 7))   # two 128-row tiles, ragged
+    if tile in (0, 128):
+        lps.append(lpgen.gen_lp(150, 331, 7))   # 64-edge tiles / two 128-row tiles, ragged
     _write(tmp_path / "in.bin", lps)
     _run(emu, "batch", tmp_path / "in.bin", tmp_path / "out.bin", 200, 0, tile)
     raw = (tmp_path / "out.bin").read_bytes()
