@@ -114,8 +114,10 @@ typedef struct lp_options {
                               correction that does not halve the previous one,
                               or an FP32 pivot that is not positive, also falls
                               back (default 5)                                   */
-  int32_t profile;         /* non-zero: time each phase with HIP events on the
-                              handle's stream (see lp_get_timings)               */
+  int32_t profile;         /* 2: time only the normal-matrix kernel with HIP
+                              events on the handle's stream (two events per
+                              iteration); any other non-zero value: time
+                              every phase (see lp_get_timings)                    */
   int32_t syrk_tile;       /* FP64 normal-matrix kernel: 0 (library's choice:
                               the stream-K kernel, 128 x 128 tiles and one
                               equal share of the work per compute unit, when

@@ -53,7 +53,8 @@ def options(alpha=0.95, precision="fp64", tape_capacity=0, mixed_switch_gap=1e-6
     o.mixed_switch_gap = float(mixed_switch_gap)
     o.refine_tol = float(refine_tol)
     o.refine_max = int(refine_max)
-    o.profile = int(bool(profile))
+    # True (or 1): every phase; "kernel" (or 2): the normal-matrix kernel alone
+    o.profile = 2 if profile in ("kernel", 2) else int(bool(profile))
     o.syrk_tile = int(syrk_tile)
     o.syrk_splits = int(syrk_splits)
     o.syrk32_splits = int(syrk32_splits)

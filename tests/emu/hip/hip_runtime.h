@@ -115,6 +115,7 @@ inline void __builtin_amdgcn_wave_barrier() { g_wave_bar[threadIdx.x >> 6].wait(
 inline void __builtin_amdgcn_sched_barrier(int) {}
 // instruction-scheduling hints: nothing to do on the host
 inline void __builtin_amdgcn_iglp_opt(int) {}
+inline void __builtin_amdgcn_s_setprio(int) {}
 // with workgroups running at once, a polling thread gives its OS thread
 // away for a moment (the producer it waits for runs on another one), so a
 // spin limit counts real time as on the hardware rather than host loop trips

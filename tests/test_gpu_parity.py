@@ -243,6 +243,32 @@ def test_determinism(torch_dev):
         np.testing.assert_array_equal(a, b)
 
 
+def test_profiling_levels(torch_dev):
+    """Timing events change no result: an unprofiled solve, one timing only
+    the normal-matrix kernel (two events per iteration) and one timing every
+    phase give bitwise identical iterates; the kernel-only level reports that
+    kernel's time for every iteration and no phase times."""
+    torch, dev = torch_dev
+    from paper_1502_03543_amd import solver
+    lp = lpgen.gen_lp(600, 1500, 11)
+    outs, tims = [], []
+    for prof in (False, "kernel", True):
+        h = solver.LP(*_lp_tensors(torch, dev, lp), alpha=0.95, profile=prof)
+        r = h.solve(1e-8, 6)
+        outs.append([v.cpu().numpy() for v in h.iterate_values()])
+        tims.append((r["iters"], h.timings()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
+    k, tk = tims[1]
+    assert tk["iterations"] == k == tk["normal_launches"] and k > 0
+    assert tk["normal_kernel_ms"] > 0
+    assert tk["potrf_ms"] == tk["trsv_ms"] == tk["iter_ms"] == tk["normal_ms"] == 0
+    _, tf = tims[2]
+    assert tf["iter_ms"] > tf["normal_kernel_ms"] > 0 and tf["potrf_ms"] > 0
+    assert tims[0][1]["iterations"] == 0
+
+
 def _golden(name):
     import json
     import os
