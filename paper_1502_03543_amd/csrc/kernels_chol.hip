@@ -612,16 +612,6 @@ __device__ __forceinline__ void potrf_panel_mfma(int mr, int mc, double* __restr
 constexpr int kPanelTPW = 1;
 constexpr int kPanelRows = PanelShape<kPanelTPW>::rows;
 
-__global__ __launch_bounds__(256) void k_potrf_panel_f64(int mr, int mc, double* __restrict__ M,
-                                                          long ld, int p,
-                                                          double* __restrict__ diag,
-                                                          DevInfo* info) {
-  __shared__ __attribute__((aligned(16))) double lds[panel_lds_doubles<kPanelTPW>()];
-  potrf_panel_mfma<kPanelTPW>(mr, mc, M, ld, p, blockIdx.x, (int)blockIdx.x - 1,
-                              diag + (long)(p / NB) * NB * NB, &info->chol_fail,
-                              reinterpret_cast<unsigned long long*>(&info->min_pivot), lds);
-}
-
 // ---------------------------------------------------------------------------
 // Trailing updates:
 //   C[i][j] -= sum_{k < K} X[i][k] X[j][k]
