@@ -84,18 +84,24 @@ def test_batch_validation(torch_dev):
         solver.Batch(lps)
 
 
-def test_batch_512_ragged(torch_dev):
+@pytest.mark.parametrize("launch", ["tuned", "default"])
+def test_batch_512_ragged(torch_dev, launch):
     """The 512-LP batch (seeds 0..511): every LP against the oracle's solve of
     that LP, stored by tests/golden/make_golden.py: same status and iteration
     count, b^T y within 1e-9 relative; converged LPs satisfy the optimality
-    properties; the 24 largest LPs are also re-solved by the oracle here."""
+    properties; the 24 largest LPs are also re-solved by the oracle here.
+    Both with the launch the bench uses (the autotuner's entry) and with the
+    library's default (per-LP tile edges, four iterations per graph)."""
     import json
     import os
     from paper_1502_03543_amd import solver
     with open(os.path.join(os.path.dirname(__file__), "golden", "batch512_seed0.json")) as f:
         gold = json.load(f)["lps"]
     lps = lpgen.gen_batch(512, first_seed=0)
-    bt = solver.Batch(lps, alpha=0.95)
+    if launch == "tuned":
+        bt = solver.Batch(lps, alpha=0.95)
+    else:
+        bt = solver.Batch(lps, alpha=0.95, batch_tile=0, batch_graph_iters=0)
     print("512 LPs set up, solving", flush=True)
     res = bt.solve(1e-8, 200)
     its = bt.iterates()
