@@ -120,6 +120,8 @@ struct lp_handle {
   enum { EV_ITER0, EV_SYRK0, EV_SYRKK0, EV_SYRKK1, EV_SYRK1, EV_CHOL1, EV_TRSV1, EV_ITER1, EV_N };
   hipEvent_t ev[EV_N] = {};
   int profiling = 0;  // 0 off, 1 every phase, 2 the normal-matrix kernel alone
+  // second stream and events of the grouped FP64 Cholesky (large m)
+  CholAux aux;
   lp_timings tim{};
 };
 
@@ -447,7 +449,7 @@ static lp_status setup_finish(lp_handle* h, const double* b, const double* c, co
       launch_iter_begin(s, h->info, h->trsv_sync, h->nblk);
       launch_syrk_f64(s, (int)m, (int)n, h->A, n, h->wb_one, h->M, h->ldm, false, h->syrk_tile,
                       h->syrk_splits, h->syrk_part);
-      launch_potrf_f64(s, (int)m, (int)m, h->M, h->ldm, h->info, h->diag);
+      launch_potrf_f64(s, (int)m, (int)m, h->M, h->ldm, h->info, h->diag, &h->aux);
       launch_wb_cols(s, (int)m, (int)n, h->M, h->ldm, h->A, h->wb_y0);
       DevInfo di{};
       e = hipMemcpyAsync(&di, h->info, sizeof(di), hipMemcpyDeviceToHost, s);
@@ -460,6 +462,14 @@ static lp_status setup_finish(lp_handle* h, const double* b, const double* c, co
     }
     if (e != hipSuccess) {
       delete h;
+      return LP_ERR_DEVICE;
+    }
+  }
+  if (chol_grouped((int)m)) {
+    if (hipStreamCreateWithFlags(&h->aux.st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->aux.ev_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->aux.ev_aux, hipEventDisableTiming) != hipSuccess) {
+      lp_destroy(h);
       return LP_ERR_DEVICE;
     }
   }
@@ -579,7 +589,7 @@ static void solve_fp64(lp_handle* h) {
   // rhs rides along as row m of the factorization: it leaves as z = L^-1 rhs
   double* zrow = h->M + (size_t)m * h->ldm;
   launch_copy(s, zrow, h->rhs, m);
-  launch_potrf_f64(s, (int)m + 1, (int)m, h->M, h->ldm, h->info, h->diag);
+  launch_potrf_f64(s, (int)m + 1, (int)m, h->M, h->ldm, h->info, h->diag, &h->aux);
   mark(h, lp_handle::EV_CHOL1);
   launch_trsv_bwd(s, (int)m, h->M, h->ldm, zrow, h->dy, h->trsv_sync, h->info);
   h->last_prec = LP_PREC_FP64;
@@ -919,7 +929,7 @@ lp_status lp_backward(lp_handle* h, const double* xbar_K, const double* ybar_K,
                     h->syrk_splits, h->syrk_part);
     double* zrow = h->M + (size_t)m * h->ldm;
     launch_copy(s, zrow, h->rhs, m);
-    launch_potrf_f64(s, (int)m + 1, (int)m, h->M, h->ldm, h->info, h->diag);
+    launch_potrf_f64(s, (int)m + 1, (int)m, h->M, h->ldm, h->info, h->diag, &h->aux);
     launch_trsv_bwd(s, (int)m, h->M, h->ldm, zrow, h->dy, h->trsv_sync, h->info);
     launch_gemv_t(s, m, n, h->A, h->dy, h->by, h->P1, h->P2);
     launch_dir(s, m, n, h->P1, h->P2, h->nchunks, h->brd, h->bx, h->bs, h->d, h->dx, h->ds,
@@ -978,6 +988,9 @@ lp_status lp_destroy(lp_handle* h) {
   if (!h) return LP_OK;
   for (int i = 0; i < lp_handle::EV_N; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  if (h->aux.ev_main) (void)hipEventDestroy(h->aux.ev_main);
+  if (h->aux.ev_aux) (void)hipEventDestroy(h->aux.ev_aux);
+  if (h->aux.st) (void)hipStreamDestroy(h->aux.st);
   delete h;
   return LP_OK;
 }
@@ -1051,12 +1064,26 @@ lp_status lp_cholesky(int64_t m, double* M, int64_t ldm, void* workspace, size_t
   lp_status st = blocks_from(m, m + 1, workspace, ws_bytes, b);
   if (st != LP_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  launch_iter_begin(s, b.info, b.sync, cdiv(m, kTB));
-  launch_potrf_f64(s, (int)m, (int)m, M, ldm, b.info, b.diag);
+  // a grouped factorization runs part of its updates on a second stream of
+  // its own, joined into s before the factorization ends
+  CholAux aux;
+  hipError_t e = hipSuccess;
+  if (chol_grouped((int)m)) {
+    e = hipStreamCreateWithFlags(&aux.st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&aux.ev_main, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&aux.ev_aux, hipEventDisableTiming);
+  }
   DevInfo di;
-  hipError_t e = hipMemcpyAsync(&di, b.info, sizeof(di), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) {
+    launch_iter_begin(s, b.info, b.sync, cdiv(m, kTB));
+    launch_potrf_f64(s, (int)m, (int)m, M, ldm, b.info, b.diag, &aux);
+    e = hipMemcpyAsync(&di, b.info, sizeof(di), hipMemcpyDeviceToHost, s);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipGetLastError();
+  if (aux.ev_main) (void)hipEventDestroy(aux.ev_main);
+  if (aux.ev_aux) (void)hipEventDestroy(aux.ev_aux);
+  if (aux.st) (void)hipStreamDestroy(aux.st);
   if (e != hipSuccess) return LP_ERR_DEVICE;
   const bool broke = di.chol_fail != INT_MAX;
   if (fail_col) *fail_col = broke ? di.chol_fail : -1;

@@ -2,15 +2,19 @@
 // names Cholesky as the usual solver for the symmetric positive definite
 // A D A^T).  Row-major lower storage, panel width kTB = 64.
 //
-// FP64, per panel p (panels grouped by four, see launch_potrf_f64):
+// FP64, per panel p (large matrices: panels grouped by four, see
+// launch_potrf_f64):
 //   1. k_chol_step: the panel step (potrf_panel_mfma: A11 and the panel rows
 //      on the matrix cores, L11 to a side buffer, the rows below solved in
-//      place) in its first workgroups and, in the others, trailing updates
-//      of the columns from p + 64 on: the previous panel's inside the group
-//      (K = 64) and the previous group's beyond it (K = 256), on 64 x 64
-//      tiles of the 16 x 16 x 4 FP64 matrix instruction;
+//      place) in its first workgroups and, in the others, the previous
+//      panel's trailing update of the columns from p + 64 on (grouped: of
+//      the rest of the group, and the previous group's of the rest of this
+//      group beside its first panel), on tiles of the 16 x 16 x 4 FP64
+//      matrix instruction;
 //   2. k_chol_col0: the next panel's 64 columns updated with panel p, or
-//      with the whole group when the next panel starts a new group.
+//      with the whole group when the next panel starts a new group;
+//   3. grouped only, at a group's end: k_chol_upd, the group's update of the
+//      columns beyond the next group, on a second stream.
 // FP32 (mixed precision): potrf_panel_body, one wavefront factoring A11 with
 // the panel rows solved by the other three, then the FP32 trailing update.
 // Rows below the last column (mr > mc) are carried through every step like
@@ -789,26 +793,41 @@ __global__ __launch_bounds__(256) void k_chol_step(int mr, int mc, double* __res
   else if (t - u1.ntiles < u2.ntiles) chol_update_tile<BM>(mr, u2, M, ld, t - u1.ntiles, lds);
 }
 
-// Update of the next panel's columns q .. q + NB - 1 (all rows from q) with
-// the factor columns kcol .. kcol + K - 1 (K = 64: the panel just factored;
-// K = 256: the group of four just finished).  This update sits on the
-// critical path between two panels, so it is cut fine and kept short: 32 x
-// 32 tiles (workgroup b takes tile (0, 0) for b = 0, else ((b + 1) / 2,
-// (b + 1) % 2)), each wavefront a 16 x 16 block on the 16 x 16 x 4 FP64
-// instruction with its operands loaded straight into registers (no LDS, no
-// barrier), 64 factor columns per round with every load of the round
-// issued at once; the accumulators start from C and the row operand is
-// negated, so the result is C - L_r L_c^T.
+// Update of the columns q .. q + W - 1 (all rows from q) with the factor
+// columns kcol .. kcol + K - 1: the next panel's 64 columns with the panel
+// just factored (K = 64), or, when the next panel starts a new group, the
+// whole next group's columns with the group just finished (K = 256).  This
+// update sits on the critical path between two panels, so it is cut fine
+// and kept short: 32 x 32 tiles of the trapezoid in row-major order (row
+// tile ti holds column tiles 0 .. min(ti, nct - 1)), each wavefront a
+// 16 x 16 block on the 16 x 16 x 4 FP64 instruction with its operands loaded
+// straight into registers (no LDS, no barrier), 64 factor columns per round
+// with every load of the round issued at once; the accumulators start from
+// C and the row operand is negated, so the result is C - L_r L_c^T (the same
+// instruction sequence per element as the LDS-staged tile routine).
 constexpr int kCol0BM = 32;
+inline int col0_tiles(int mr, int q, int W) {
+  const int nrt = cdiv(mr - q, kCol0BM), nct = cdiv(W, kCol0BM);
+  return nrt >= nct ? trap_tiles(nrt, nct) : nrt * (nrt + 1) / 2;
+}
 __global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ M, long ld, int q,
-                                                   int kcol, int K) {
-  const int b = blockIdx.x;
-  const int ti = (b + 1) / 2, tj = b == 0 ? 0 : (b + 1) % 2;
+                                                   int W, int kcol, int K) {
+  const int b = blockIdx.x, nct = (W + kCol0BM - 1) / kCol0BM, t0 = nct * (nct + 1) / 2;
+  int ti, tj;
+  if (b < t0) {
+    ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    tj = b - ti * (ti + 1) / 2;
+  } else {
+    ti = nct + (b - t0) / nct;
+    tj = (b - t0) % nct;
+  }
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int r0 = q + kCol0BM * ti + 16 * (wv >> 1);  // the wavefront's block rows
   const int c0 = q + kCol0BM * tj + 16 * (wv & 1);   // and columns
-  if (c0 > r0 + 15 || r0 >= mr) return;              // above the diagonal, or below the matrix
+  // above the diagonal, below the matrix or beyond the W columns
+  if (c0 > r0 + 15 || r0 >= mr || c0 >= q + W) return;
   const double* pa = M + (long)min(r0 + li, mr - 1) * ld + kcol + lk;
   const double* pb = M + (long)min(c0 + li, mr - 1) * ld + kcol + lk;
   mf4 acc;
@@ -830,8 +849,19 @@ __global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ 
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int gr = r0 + lk + 4 * v, gc = c0 + li;
-    if (gr < mr && gc <= gr) M[(long)gr * ld + gc] = acc[v];
+    if (gr < mr && gc <= gr && gc < q + W) M[(long)gr * ld + gc] = acc[v];
   }
+}
+
+// A trailing update on its own (the grouped schedule's update of the columns
+// beyond the next group, on the second stream): tile b of u, XCD-aware.
+template <int BM>
+__global__ __launch_bounds__(256) void k_chol_upd(int mr, double* __restrict__ M, long ld,
+                                                  CholUpd u, int per_xcd) {
+  __shared__ __attribute__((aligned(16))) double lds[up_lds_doubles<BM>()];
+  const int b = blockIdx.x;
+  const int t = (b & 7) * per_xcd + (b >> 3);
+  if (t < u.ntiles) chol_update_tile<BM>(mr, u, M, ld, t, lds);
 }
 
 __global__ __launch_bounds__(256) void k_potrf_panel_f32(int mr, int mc, float* __restrict__ M,
@@ -927,25 +957,28 @@ __global__ __launch_bounds__(256) void k_bdiag_to_m(const BatchLP* __restrict__ 
 
 // Right-looking schedule over panels of NB = 64 columns, optionally grouped
 // by G panels.  With G = 1 every step applies the previous panel to all
-// later columns (K = 64).  With G > 1 a panel's update of the columns inside
-// its own group is applied at once (K = 64); its update of the columns
-// beyond the group is deferred and applied with the rest of the group as one
-// K = 64 G update, so the trailing matrix is read and written once per
-// group instead of once per panel.  For panel k = G g + j at column p (group
-// columns gs .. ge):
-//   step launch k: the panel, and beside it
-//     j >= 1: panel k - 1 on columns [p + 64, ge)                (K = 64)
-//     g >= 1: group g - 1 on columns [p + 64, ge)   when j = 0,  (K = 64 G)
-//             or on part j of G - 1 parts of [ge, mc) when j >= 1
-//             (with G = 1: on [p + 64, mc));
-//   then a column update of the next panel's 64 columns: panel k (K = 64)
-//   inside the group, or group g (K = 64 G) when the next panel starts the
-//   next group.
-// Every update reads finished factor columns only and no two parts of one
-// launch write the same columns; each panel's columns have received every
+// later columns (K = 64), beside the next panel.  With G > 1 a panel's
+// update of the columns inside its own group is applied at once (K = 64);
+// its update of the columns beyond the group is deferred and applied with
+// the rest of the group as one K = 64 G update, so the trailing matrix is
+// read and written once per group instead of once per panel.  For panel
+// k = G g + j at column p (group columns gs .. ge):
+//   step launch k: the panel, and beside it panel k - 1 on [p + 64, ge)
+//     when j >= 1 (K = 64);
+//     and group g - 1 (K = 64 G) on [p + 64, ge) when j = 0 and g >= 1;
+//   then a column update of the next panel's 64 columns: panel k inside the
+//   group, group g (K = 64 G) after the group's last panel, when group g's
+//   update of the columns beyond the next group, [ne, mc), also starts on
+//   the second stream, beside the next group's panels (a K = 256 tile takes
+//   about as long as three panel steps, so a schedule that put those tiles
+//   into the steps made every step wait for one).
+// Every update reads finished factor columns only, no two concurrent
+// launches write the same columns, and each element receives the updates in
+// the same order and with the same instruction sequence whichever stream
+// and tile routine apply them; each panel's columns have received every
 // earlier panel's contribution when its step starts.
 namespace {
-constexpr int kCholGroupMinM = 4096;
+int chol_group_min_m = 4096;
 CholUpd make_upd(int bm, int mr, int c0, int c1, int kcol, int K) {
   CholUpd u{};
   u.c0 = c0;
@@ -958,12 +991,26 @@ CholUpd make_upd(int bm, int mr, int c0, int c1, int kcol, int K) {
 }
 }  // namespace
 
+bool chol_grouped(int mc) { return mc >= chol_group_min_m; }
+void set_chol_group_min_m(int m) { chol_group_min_m = m; }
+
 void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInfo* info,
-                      double* diag) {
+                      double* diag, const CholAux* aux) {
   // grouping pays where the trailing update is bound by its traffic (large
   // m); below that the per-panel update hides behind the panel itself
-  const bool big = mc >= kCholGroupMinM;
+  const bool big = chol_grouped(mc);
   const int G = big ? 4 : 1, GW = G * NB, bm = big ? 128 : 64;
+  bool two = big && aux && aux->st && aux->ev_main && aux->ev_aux;
+  hipStream_t sb = two ? aux->st : st;
+  bool aux_pending = false;  // an update on the second stream not yet waited for
+  // should an event call fail, the second stream is drained from the host
+  // and the rest of the factorization runs in order on st
+  auto drop_aux = [&]() {
+    (void)hipStreamSynchronize(sb);
+    two = false;
+    sb = st;
+    aux_pending = false;
+  };
   for (int p = 0; p < mc; p += NB) {
     const int k = p / NB, g = k / G, j = k % G;
     const int gs = g * GW, ge = gs + GW < mc ? gs + GW : mc;
@@ -972,19 +1019,9 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
     const CholUpd none = make_upd(bm, mr, 0, 0, 0, NB);
     CholUpd u1 = none, u2 = none;
     if (j >= 1) u1 = make_upd(bm, mr, p + NB, ge, p - NB, NB);
-    if (g >= 1) {
-      if (G == 1) {
-        u2 = make_upd(bm, mr, p + NB, mc, gs - GW, GW);
-      } else if (j == 0) {
-        u2 = make_upd(bm, mr, p + NB, ge, gs - GW, GW);
-      } else {
-        // part j of the later columns, in whole 64-column tiles
-        const int ntc = cdiv(mc - ge, NB);
-        const int a = ge + NB * ((ntc * (j - 1)) / (G - 1));
-        const int b = j == G - 1 ? mc : ge + NB * ((ntc * j) / (G - 1));
-        if (b > a) u2 = make_upd(bm, mr, a, b, gs - GW, GW);
-      }
-    }
+    // G = 1: the previous panel on all later columns; grouped: the previous
+    // group on the rest of this group's columns, beside its first panel
+    if (g >= 1 && (G == 1 || j == 0)) u2 = make_upd(bm, mr, p + NB, G == 1 ? mc : ge, gs - GW, GW);
     const int ntiles = u1.ntiles + u2.ntiles;
     const int per_xcd = cdiv(ntiles, 8);
     const int npw = ntiles ? cdiv(npw_need, 8) * 8 : npw_need;
@@ -995,12 +1032,39 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
       hipLaunchKernelGGL(k_chol_step<64>, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M,
                          ld, p, diag, info, npw_need, npw, u1, u2, per_xcd);
     const int q = p + NB;
-    if (q < mc) {
-      const bool group_end = (q == ge);
-      hipLaunchKernelGGL(k_chol_col0, dim3(2 * cdiv(mr - q, kCol0BM) - 1), dim3(256), 0, st, mr,
-                         M, ld, q, group_end ? gs : p, group_end ? GW : NB);
+    if (q >= mc) continue;
+    if (!big || q < ge) {
+      // the next panel's 64 columns with this panel
+      hipLaunchKernelGGL(k_chol_col0, dim3(col0_tiles(mr, q, NB)), dim3(256), 0, st, mr, M, ld,
+                         q, NB, p, NB);
+      continue;
     }
+    // Group g is finished (its factor columns are final).  Its update of the
+    // columns beyond the next group goes to the second stream, beside the
+    // next group's panels, which write only their own columns; the next
+    // group's first panel gets it from the column update and the rest of
+    // that group from the first step, both after the previous group's update
+    // of them (on the second stream) has ended.
+    const int ne = ge + GW < mc ? ge + GW : mc;
+    if (two && (hipEventRecord(aux->ev_main, st) != hipSuccess ||
+                hipStreamWaitEvent(sb, aux->ev_main, 0) != hipSuccess))
+      drop_aux();
+    if (ne < mc) {
+      const CholUpd uo = make_upd(bm, mr, ne, mc, gs, GW);
+      const int px = cdiv(uo.ntiles, 8);
+      hipLaunchKernelGGL(k_chol_upd<128>, dim3(8 * px), dim3(256), 0, sb, mr, M, ld, uo, px);
+    }
+    if (two && aux_pending && hipStreamWaitEvent(st, aux->ev_aux, 0) != hipSuccess) drop_aux();
+    if (two) {
+      if (hipEventRecord(aux->ev_aux, sb) != hipSuccess)
+        drop_aux();
+      else
+        aux_pending = ne < mc;
+    }
+    hipLaunchKernelGGL(k_chol_col0, dim3(col0_tiles(mr, q, NB)), dim3(256), 0, st, mr, M, ld, q,
+                       NB, gs, GW);
   }
+  if (two && aux_pending && hipStreamWaitEvent(st, aux->ev_aux, 0) != hipSuccess) drop_aux();
   hipLaunchKernelGGL(k_diag_to_m<double>, dim3(cdiv(mc, NB)), dim3(256), 0, st, mc, M, ld, diag);
 }
 

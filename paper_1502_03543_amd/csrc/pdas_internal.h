@@ -131,8 +131,21 @@ void syrk_choose_f32(int mm, int K, int* splits);
 // fused into the factorization).  With mr > mc the trailing updates also
 // write the entries (r, c) of those rows for c <= r, so ld must exceed mr - 1.
 inline long potrf_diag_elems(long m) { return (long)cdiv(m, kTB) * kTB * kTB; }
+// Large factorizations (chol_grouped(mc)) group the panels by four; each
+// group's update of the columns beyond the next group then runs on a second
+// stream beside the next group's panels when aux is given (both events
+// without timing; the factor is the same bit for bit either way).  Without
+// aux that update runs in order on st.
+struct CholAux {
+  hipStream_t st = nullptr;
+  hipEvent_t ev_main = nullptr, ev_aux = nullptr;
+};
+bool chol_grouped(int mc);
+// The grouping threshold (columns); lowered only by the CPU emulation of
+// the kernels, so that small matrices take the grouped schedule there.
+void set_chol_group_min_m(int m);
 void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInfo* info,
-                      double* diag);
+                      double* diag, const CholAux* aux = nullptr);
 void launch_potrf_f32(hipStream_t st, int m, float* M, long ld, DevInfo* info, float* diag);
 
 // --- triangular solves (kernels_trsv.hip) ----------------------------------

@@ -1,8 +1,9 @@
 // Host drivers for the emulated kernels (test infrastructure only).
-//   emu chol <m>                      lower Cholesky of a fixed SPD matrix with
+//   emu chol <m> [g]                  lower Cholesky of a fixed SPD matrix with
 //                                     one extra right-hand-side row; prints
 //                                     the factor and forward-solve errors
-//                                     against a long-double reference
+//                                     against a long-double reference; g > 0
+//                                     lowers the grouping threshold to g
 //   emu syrk <m> <n> <tile> <splits>  normal matrix (tile 0: stream-K), against a
 //                                     long-double reference
 //   emu trsv <m>                      L z = r and L^T y = z with a fixed
@@ -53,7 +54,9 @@ extern "C" void lp_options_default(lp_options* o) {
 // garbage) counts as infinite; std::fmax would drop it
 static double worse(double acc, double e) { return (e <= acc) ? acc : (std::isnan(e) ? INFINITY : e); }
 
-static int run_chol(int m) {
+static int run_chol(int m, int group_min_m) {
+  // a lower grouping threshold takes small matrices through the grouped schedule
+  if (group_min_m > 0) pdas::set_chol_group_min_m(group_min_m);
   const long ld = (m + 1 + 7) / 8 * 8;
   std::vector<double> A((size_t)(m + 1) * ld, NAN);  // upper part never read
   for (int i = 0; i < m; ++i)
@@ -381,7 +384,8 @@ static int run_sparse(int m, int n, int pattern) {
 }
 
 int main(int argc, char** argv) {
-  if (argc >= 3 && !strcmp(argv[1], "chol")) return run_chol(atoi(argv[2]));
+  if (argc >= 3 && !strcmp(argv[1], "chol"))
+    return run_chol(atoi(argv[2]), argc >= 4 ? atoi(argv[3]) : 0);
   if (argc >= 6 && !strcmp(argv[1], "syrk"))
     return run_syrk(atoi(argv[2]), atoi(argv[3]), atoi(argv[4]), atoi(argv[5]));
   if (argc >= 3 && !strcmp(argv[1], "trsv")) return run_trsv(atoi(argv[2]));
@@ -390,6 +394,6 @@ int main(int argc, char** argv) {
   if (argc >= 6 && !strcmp(argv[1], "batch"))
     return run_batch(argv[2], argv[3], atoi(argv[4]), atoi(argv[5]), argc >= 7 ? atoi(argv[6]) : 0,
                      argc >= 8 ? atoi(argv[7]) : 0);
-  fprintf(stderr, "usage: emu chol <m> | emu batch <in> <out> <max_iter> <tape>\n");
+  fprintf(stderr, "usage: emu chol <m> [g] | emu batch <in> <out> <max_iter> <tape>\n");
   return 1;
 }

@@ -43,9 +43,15 @@ def _run(exe, *args, timeout=600, interleave=1):
     return p.stdout
 
 
-@pytest.mark.parametrize("m", [40, 64, 100, 150, 300, 700, 1100])
-def test_emulated_cholesky_with_fused_forward_solve(emu, m):
-    r = json.loads(_run(emu, "chol", m).strip().splitlines()[-1])
+@pytest.mark.parametrize("m,group", [(40, 0), (64, 0), (100, 0), (150, 0), (300, 0), (700, 0),
+                                     (1100, 0), (300, 128), (700, 256), (1100, 256)])
+def test_emulated_cholesky_with_fused_forward_solve(emu, m, group):
+    """group > 0: the grouped schedule of large matrices (panels by four, the
+    group's update of the columns beyond the next group as a launch of its
+    own, the next group's columns in one column update) at a small m: with
+    300 the second group is the last (no update beyond it); 700 and 1100 end
+    in a ragged group."""
+    r = json.loads(_run(emu, "chol", m, group).strip().splitlines()[-1])
     assert r["fail"] == -1
     assert r["factor_rel_err"] <= 1e-13, r
     assert r["solve_rel_err"] <= 1e-13, r
