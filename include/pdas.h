@@ -27,7 +27,11 @@
  *    device workspace, sized by lp_workspace_size / lp_batch_workspace_size,
  *    that the library carves up.  Handles themselves are small host objects.
  *  - All device work is ordered on the stream given to lp_setup.  Functions
- *    that return host values (info, results) synchronise that stream.
+ *    that return host values (info, results) synchronise that stream.  A
+ *    handle with m >= 4096 also owns a second stream (default priority) and
+ *    two events: part of each factorization's trailing update runs there,
+ *    and the caller's stream waits for it before the factorization ends, so
+ *    the ordering seen by the caller is unchanged.  lp_destroy releases them.
  *  - One handle must not be used from two host threads at once.
  *  - Nothing throws or aborts across this ABI: every function returns an
  *    lp_status; on an error the handle keeps its last valid iterate.
@@ -402,7 +406,9 @@ lp_status lp_normal_matrix(int64_t m, int64_t n, const double* A, const double* 
                            int64_t ldm, void* workspace, size_t ws_bytes, lp_stream_t stream);
 
 /* In-place Cholesky M = L L^T (Section 5.1) of the lower triangle of M
- * (device, row-major, ldm).  Synchronises; *fail_col (host, nullable)
+ * (device, row-major, ldm).  For m >= 4096 the call creates a second stream
+ * and two events for the duration of the factorization (LP_ERR_DEVICE if
+ * that fails).  Synchronises; *fail_col (host, nullable)
  * receives -1, or the first column whose pivot is not a finite positive
  * number (then LP_ERR_BREAKDOWN is returned and M holds partial results);
  * *min_pivot (host, nullable) the smallest accepted pivot. */
