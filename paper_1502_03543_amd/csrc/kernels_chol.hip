@@ -1016,16 +1016,20 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
     const int gs = g * GW, ge = gs + GW < mc ? gs + GW : mc;
     const int nbe = (mc - p) < NB ? (mc - p) : NB;
     const int npw_need = 1 + cdiv(mr - p - nbe, kPanelRows);
-    const CholUpd none = make_upd(bm, mr, 0, 0, 0, NB);
+    // grouped: the previous group's K = 256 update of the rest of this
+    // group's columns sits beside the group's first panel, on the critical
+    // path, so that step takes 64-edge tiles (a quarter of the work each)
+    const int sbm = (big && j == 0 && g >= 1) ? 64 : bm;
+    const CholUpd none = make_upd(sbm, mr, 0, 0, 0, NB);
     CholUpd u1 = none, u2 = none;
-    if (j >= 1) u1 = make_upd(bm, mr, p + NB, ge, p - NB, NB);
+    if (j >= 1) u1 = make_upd(sbm, mr, p + NB, ge, p - NB, NB);
     // G = 1: the previous panel on all later columns; grouped: the previous
     // group on the rest of this group's columns, beside its first panel
-    if (g >= 1 && (G == 1 || j == 0)) u2 = make_upd(bm, mr, p + NB, G == 1 ? mc : ge, gs - GW, GW);
+    if (g >= 1 && (G == 1 || j == 0)) u2 = make_upd(sbm, mr, p + NB, G == 1 ? mc : ge, gs - GW, GW);
     const int ntiles = u1.ntiles + u2.ntiles;
     const int per_xcd = cdiv(ntiles, 8);
     const int npw = ntiles ? cdiv(npw_need, 8) * 8 : npw_need;
-    if (big)
+    if (sbm == 128)
       hipLaunchKernelGGL(k_chol_step<128>, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M,
                          ld, p, diag, info, npw_need, npw, u1, u2, per_xcd);
     else
