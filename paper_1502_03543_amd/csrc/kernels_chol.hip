@@ -854,15 +854,19 @@ __global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ 
 }
 
 // A trailing update on its own (the grouped schedule's update of the columns
-// beyond the next group, on the second stream): tile b of u, XCD-aware.
+// beyond the next group, on the second stream): at most one workgroup per
+// compute unit, each taking every gridDim.x-th tile, so that the panels and
+// column updates of the other stream always find room beside it.
 template <int BM>
 __global__ __launch_bounds__(256) void k_chol_upd(int mr, double* __restrict__ M, long ld,
-                                                  CholUpd u, int per_xcd) {
+                                                  CholUpd u) {
   __shared__ __attribute__((aligned(16))) double lds[up_lds_doubles<BM>()];
-  const int b = blockIdx.x;
-  const int t = (b & 7) * per_xcd + (b >> 3);
-  if (t < u.ntiles) chol_update_tile<BM>(mr, u, M, ld, t, lds);
+  for (int t = blockIdx.x; t < u.ntiles; t += gridDim.x) {
+    chol_update_tile<BM>(mr, u, M, ld, t, lds);
+    __syncthreads();  // the next tile restages the LDS buffers
+  }
 }
+constexpr int kUpdGroups = 256;
 
 __global__ __launch_bounds__(256) void k_potrf_panel_f32(int mr, int mc, float* __restrict__ M,
                                                           long ld, int p, float* __restrict__ diag,
@@ -1055,8 +1059,8 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
       drop_aux();
     if (ne < mc) {
       const CholUpd uo = make_upd(bm, mr, ne, mc, gs, GW);
-      const int px = cdiv(uo.ntiles, 8);
-      hipLaunchKernelGGL(k_chol_upd<128>, dim3(8 * px), dim3(256), 0, sb, mr, M, ld, uo, px);
+      const int gx = uo.ntiles < kUpdGroups ? uo.ntiles : kUpdGroups;
+      hipLaunchKernelGGL(k_chol_upd<128>, dim3(gx), dim3(256), 0, sb, mr, M, ld, uo);
     }
     if (two && aux_pending && hipStreamWaitEvent(st, aux->ev_aux, 0) != hipSuccess) drop_aux();
     if (two) {
