@@ -793,41 +793,26 @@ __global__ __launch_bounds__(256) void k_chol_step(int mr, int mc, double* __res
   else if (t - u1.ntiles < u2.ntiles) chol_update_tile<BM>(mr, u2, M, ld, t - u1.ntiles, lds);
 }
 
-// Update of the columns q .. q + W - 1 (all rows from q) with the factor
-// columns kcol .. kcol + K - 1: the next panel's 64 columns with the panel
-// just factored (K = 64), or, when the next panel starts a new group, the
-// whole next group's columns with the group just finished (K = 256).  This
-// update sits on the critical path between two panels, so it is cut fine
-// and kept short: 32 x 32 tiles of the trapezoid in row-major order (row
-// tile ti holds column tiles 0 .. min(ti, nct - 1)), each wavefront a
-// 16 x 16 block on the 16 x 16 x 4 FP64 instruction with its operands loaded
-// straight into registers (no LDS, no barrier), 64 factor columns per round
-// with every load of the round issued at once; the accumulators start from
-// C and the row operand is negated, so the result is C - L_r L_c^T (the same
-// instruction sequence per element as the LDS-staged tile routine).
+// Update of the next panel's columns q .. q + NB - 1 (all rows from q) with
+// the factor columns kcol .. kcol + K - 1 (K = 64: the panel just factored;
+// K = 256: the group of four just finished).  This update sits on the
+// critical path between two panels, so it is cut fine and kept short: 32 x
+// 32 tiles (workgroup b takes tile (0, 0) for b = 0, else ((b + 1) / 2,
+// (b + 1) % 2)), each wavefront a 16 x 16 block on the 16 x 16 x 4 FP64
+// instruction with its operands loaded straight into registers (no LDS, no
+// barrier), 64 factor columns per round with every load of the round
+// issued at once; the accumulators start from C and the row operand is
+// negated, so the result is C - L_r L_c^T.
 constexpr int kCol0BM = 32;
-inline int col0_tiles(int mr, int q, int W) {
-  const int nrt = cdiv(mr - q, kCol0BM), nct = cdiv(W, kCol0BM);
-  return nrt >= nct ? trap_tiles(nrt, nct) : nrt * (nrt + 1) / 2;
-}
 __global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ M, long ld, int q,
-                                                   int W, int kcol, int K) {
-  const int b = blockIdx.x, nct = (W + kCol0BM - 1) / kCol0BM, t0 = nct * (nct + 1) / 2;
-  int ti, tj;
-  if (b < t0) {
-    ti = 0;
-    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
-    tj = b - ti * (ti + 1) / 2;
-  } else {
-    ti = nct + (b - t0) / nct;
-    tj = (b - t0) % nct;
-  }
+                                                   int kcol, int K) {
+  const int b = blockIdx.x;
+  const int ti = (b + 1) / 2, tj = b == 0 ? 0 : (b + 1) % 2;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int r0 = q + kCol0BM * ti + 16 * (wv >> 1);  // the wavefront's block rows
   const int c0 = q + kCol0BM * tj + 16 * (wv & 1);   // and columns
-  // above the diagonal, below the matrix or beyond the W columns
-  if (c0 > r0 + 15 || r0 >= mr || c0 >= q + W) return;
+  if (c0 > r0 + 15 || r0 >= mr) return;              // above the diagonal, or below the matrix
   const double* pa = M + (long)min(r0 + li, mr - 1) * ld + kcol + lk;
   const double* pb = M + (long)min(c0 + li, mr - 1) * ld + kcol + lk;
   mf4 acc;
@@ -849,7 +834,7 @@ __global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ 
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int gr = r0 + lk + 4 * v, gc = c0 + li;
-    if (gr < mr && gc <= gr && gc < q + W) M[(long)gr * ld + gc] = acc[v];
+    if (gr < mr && gc <= gr) M[(long)gr * ld + gc] = acc[v];
   }
 }
 
@@ -1043,8 +1028,8 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
     if (q >= mc) continue;
     if (!big || q < ge) {
       // the next panel's 64 columns with this panel
-      hipLaunchKernelGGL(k_chol_col0, dim3(col0_tiles(mr, q, NB)), dim3(256), 0, st, mr, M, ld,
-                         q, NB, p, NB);
+      hipLaunchKernelGGL(k_chol_col0, dim3(2 * cdiv(mr - q, kCol0BM) - 1), dim3(256), 0, st, mr,
+                         M, ld, q, p, NB);
       continue;
     }
     // Group g is finished (its factor columns are final).  Its update of the
@@ -1069,8 +1054,8 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
       else
         aux_pending = ne < mc;
     }
-    hipLaunchKernelGGL(k_chol_col0, dim3(col0_tiles(mr, q, NB)), dim3(256), 0, st, mr, M, ld, q,
-                       NB, gs, GW);
+    hipLaunchKernelGGL(k_chol_col0, dim3(2 * cdiv(mr - q, kCol0BM) - 1), dim3(256), 0, st, mr, M,
+                       ld, q, gs, GW);
   }
   if (two && aux_pending && hipStreamWaitEvent(st, aux->ev_aux, 0) != hipSuccess) drop_aux();
   hipLaunchKernelGGL(k_diag_to_m<double>, dim3(cdiv(mc, NB)), dim3(256), 0, st, mc, M, ld, diag);

@@ -46,9 +46,10 @@ def _run(exe, *args, timeout=600, interleave=1):
 @pytest.mark.parametrize("m,group", [(40, 0), (64, 0), (100, 0), (150, 0), (300, 0), (700, 0),
                                      (1100, 0), (300, 128), (700, 256), (1100, 256)])
 def test_emulated_cholesky_with_fused_forward_solve(emu, m, group):
-    """group > 0: the grouped schedule of large matrices (panels by four, the
-    group's update of the columns beyond the next group as a launch of its
-    own, the next group's columns in one column update) at a small m: with
+    """group > 0: the grouped schedule of large matrices (panels by four; at a
+    group's end its update of the next panel's columns, of the rest of the
+    next group beside that group's first panel on 64-edge tiles, and of the
+    columns beyond the next group as a launch of its own) at a small m: with
     300 the second group is the last (no update beyond it); 700 and 1100 end
     in a ragged group."""
     r = json.loads(_run(emu, "chol", m, group).strip().splitlines()[-1])
