@@ -60,7 +60,7 @@ def test_cholesky_and_solve(torch_dev, m):
     """Factor and solve against the oracle; m = 4133 takes the grouped
     schedule of large matrices (panels by four, each group's update of the
     columns beyond the next group on a second stream), ending in a ragged
-    group."""
+    group, and is factored twice to the same bits."""
     torch, dev = torch_dev
     from paper_1502_03543_amd import solver
     rng = np.random.default_rng(m)
@@ -70,6 +70,11 @@ def test_cholesky_and_solve(torch_dev, m):
     Lg, fail, minp, st = solver.cholesky(_t(torch, dev, np.tril(M)))
     assert st == capi.LP_OK and fail == -1
     Lg = Lg.cpu().numpy()
+    if m >= 4096:
+        # the grouped schedule's two streams: the factor is the same bit for
+        # bit from one run to the next
+        Lg2, _, _, _ = solver.cholesky(_t(torch, dev, np.tril(M)))
+        assert np.array_equal(Lg, Lg2.cpu().numpy())
     Lo, fo, mpo = oracle.cholesky(M)
     assert fo == -1
     kappa = np.linalg.cond(M)
