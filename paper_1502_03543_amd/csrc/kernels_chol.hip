@@ -629,9 +629,9 @@ constexpr int kPanelRows = PanelShape<kPanelTPW>::rows;
 // doubles.  The accumulators start from the C values (loaded beside the
 // first stage, so their latency overlaps it) and the row operand is staged
 // negated, so the matrix instructions leave C - X X^T directly.
-// BM = 128 where the updates are large (fewer, longer tiles: each operand
-// row is reused by twice the columns); BM = 64 where they must finish within
-// one panel step (twice the workgroups of a quarter of the work each)
+// BM = 128 for the grouped schedule's large update on the second stream
+// (fewer, longer tiles: each operand row is reused by twice the columns);
+// BM = 64 beside a panel, where the update must finish within the step.
 constexpr int kUpKC = 16, kUpLS = kUpKC + 2;
 template <int BM>
 constexpr int up_lds_doubles() {
@@ -662,14 +662,19 @@ __device__ inline void trap_coords(int t, int nrt, int& ti, int& tj) {
   ti = tj + t;
 }
 
-template <int BM>
+// NT threads: 256 (2 x 2 wavefronts of BM/2 x BM/2) or 512 (2 x 4
+// wavefronts of BM/2 x BM/4, two per SIMD, for a launch with one workgroup
+// per compute unit); the per-element arithmetic is the same either way.
+template <int BM, int NT = 256>
 __device__ __forceinline__ void chol_update_tile(int mr, const CholUpd& u, double* __restrict__ M,
                                                  long ld, int t, double* __restrict__ lds) {
   typedef double upd4 __attribute__((ext_vector_type(4)));
+  static_assert(NT == 256 || NT == 512, "2 x 2 or 2 x 4 wavefronts");
   constexpr int PPR = kUpKC / 2;              // element pairs per row per stage
-  constexpr int PAIRS = BM * PPR / 256;       // pairs per thread per operand
-  constexpr int WB = BM / 2;                  // wavefront block side
-  constexpr int NB4 = WB / 16;                // 16 x 16 blocks per wavefront side
+  constexpr int PAIRS = BM * PPR / NT;        // pairs per thread per operand
+  constexpr int WCS = NT / 128;               // wavefront columns
+  constexpr int WR = BM / 2, WC = BM / WCS;   // wavefront block rows and columns
+  constexpr int NBR = WR / 16, NBC = WC / 16; // 16 x 16 blocks per wavefront
   int ti, tj;
   trap_coords(t, u.nrt, ti, tj);
   const int mm = mr - u.c0;
@@ -678,14 +683,14 @@ __device__ __forceinline__ void chol_update_tile(int mr, const CholUpd& u, doubl
   double* C = M + (long)u.c0 * ld + u.c0;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr0 = (wv >> 1) * WB, wc0 = (wv & 1) * WB;
+  const int wr0 = (wv / WCS) * WR, wc0 = (wv % WCS) * WC;
   // a wavefront whose block lies above the diagonal of a diagonal tile idles
-  const bool active = !(ti == tj && wr0 + WB <= wc0);
-  upd4 acc[NB4][NB4];
+  const bool active = !(ti == tj && wr0 + WR <= wc0);
+  upd4 acc[NBR][NBC];
 #pragma unroll
-  for (int r = 0; r < NB4; ++r)
+  for (int r = 0; r < NBR; ++r)
 #pragma unroll
-    for (int c = 0; c < NB4; ++c)
+    for (int c = 0; c < NBC; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gr = min(row0 + wr0 + 16 * r + lk + 4 * v, mm - 1);
@@ -699,7 +704,7 @@ __device__ __forceinline__ void chol_update_tile(int mr, const CholUpd& u, doubl
   auto gload = [&](int st) {
 #pragma unroll
     for (int it = 0; it < PAIRS; ++it) {
-      const int q = tid + 256 * it;
+      const int q = tid + NT * it;
       const int row = q / PPR, k = st * kUpKC + 2 * (q % PPR);
       const long ra = min(row0 + row, mm - 1), rb = min(col0 + row, mm - 1);
       pa[it] = *reinterpret_cast<const double2*>(X + ra * ld + k);
@@ -709,7 +714,7 @@ __device__ __forceinline__ void chol_update_tile(int mr, const CholUpd& u, doubl
   auto sstore = [&](int b) {
 #pragma unroll
     for (int it = 0; it < PAIRS; ++it) {
-      const int q = tid + 256 * it;
+      const int q = tid + NT * it;
       const int row = q / PPR, kk = 2 * (q % PPR);
       // element-wise selects (a select of whole vectors went through memory)
       const bool va = row0 + row < mm, vb = col0 + row < mm;
@@ -734,15 +739,15 @@ __device__ __forceinline__ void chol_update_tile(int mr, const CholUpd& u, doubl
       const double* lb = buf[cur][1];
 #pragma unroll
       for (int ks = 0; ks < kUpKC / 4; ++ks) {
-        double a[NB4], b[NB4];
+        double a[NBR], b[NBC];
 #pragma unroll
-        for (int r = 0; r < NB4; ++r) a[r] = la[(wr0 + 16 * r + li) * kUpLS + 4 * ks + lk];
+        for (int r = 0; r < NBR; ++r) a[r] = la[(wr0 + 16 * r + li) * kUpLS + 4 * ks + lk];
 #pragma unroll
-        for (int c = 0; c < NB4; ++c) b[c] = lb[(wc0 + 16 * c + li) * kUpLS + 4 * ks + lk];
+        for (int c = 0; c < NBC; ++c) b[c] = lb[(wc0 + 16 * c + li) * kUpLS + 4 * ks + lk];
 #pragma unroll
-        for (int r = 0; r < NB4; ++r)
+        for (int r = 0; r < NBR; ++r)
 #pragma unroll
-          for (int c = 0; c < NB4; ++c)
+          for (int c = 0; c < NBC; ++c)
             acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
       }
     }
@@ -751,9 +756,9 @@ __device__ __forceinline__ void chol_update_tile(int mr, const CholUpd& u, doubl
   }
   if (!active) return;
 #pragma unroll
-  for (int r = 0; r < NB4; ++r)
+  for (int r = 0; r < NBR; ++r)
 #pragma unroll
-    for (int c = 0; c < NB4; ++c)
+    for (int c = 0; c < NBC; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gr = row0 + wr0 + 16 * r + lk + 4 * v, gc = col0 + wc0 + 16 * c + li;
@@ -841,13 +846,15 @@ __global__ __launch_bounds__(256) void k_chol_col0(int mr, double* __restrict__ 
 // A trailing update on its own (the grouped schedule's update of the columns
 // beyond the next group, on the second stream): at most one workgroup per
 // compute unit, each taking every gridDim.x-th tile, so that the panels and
-// column updates of the other stream always find room beside it.
+// column updates of the other stream always find room beside it; eight
+// wavefronts per workgroup, so that each SIMD still has two (151 registers
+// each: a 64-edge fused step's wavefront, 158, fits beside them).
 template <int BM>
-__global__ __launch_bounds__(256) void k_chol_upd(int mr, double* __restrict__ M, long ld,
-                                                  CholUpd u) {
+__global__ __launch_bounds__(512) void k_chol_upd(
+    int mr, double* __restrict__ M, long ld, CholUpd u) {
   __shared__ __attribute__((aligned(16))) double lds[up_lds_doubles<BM>()];
   for (int t = blockIdx.x; t < u.ntiles; t += gridDim.x) {
-    chol_update_tile<BM>(mr, u, M, ld, t, lds);
+    chol_update_tile<BM, 512>(mr, u, M, ld, t, lds);
     __syncthreads();  // the next tile restages the LDS buffers
   }
 }
@@ -988,7 +995,7 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
   // grouping pays where the trailing update is bound by its traffic (large
   // m); below that the per-panel update hides behind the panel itself
   const bool big = chol_grouped(mc);
-  const int G = big ? 4 : 1, GW = G * NB, bm = big ? 128 : 64;
+  const int G = big ? 4 : 1, GW = G * NB;
   bool two = big && aux && aux->st && aux->ev_main && aux->ev_aux;
   hipStream_t sb = two ? aux->st : st;
   bool aux_pending = false;  // an update on the second stream not yet waited for
@@ -1005,25 +1012,21 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
     const int gs = g * GW, ge = gs + GW < mc ? gs + GW : mc;
     const int nbe = (mc - p) < NB ? (mc - p) : NB;
     const int npw_need = 1 + cdiv(mr - p - nbe, kPanelRows);
-    // grouped: the previous group's K = 256 update of the rest of this
-    // group's columns sits beside the group's first panel, on the critical
-    // path, so that step takes 64-edge tiles (a quarter of the work each)
-    const int sbm = (big && j == 0 && g >= 1) ? 64 : bm;
-    const CholUpd none = make_upd(sbm, mr, 0, 0, 0, NB);
+    // the updates beside a panel are on the critical path (grouped: the
+    // previous group's K = 256 update of the rest of the group beside its
+    // first panel), so they take 64-edge tiles, a quarter of the work each;
+    // their registers also leave room beside the second stream's update
+    const CholUpd none = make_upd(64, mr, 0, 0, 0, NB);
     CholUpd u1 = none, u2 = none;
-    if (j >= 1) u1 = make_upd(sbm, mr, p + NB, ge, p - NB, NB);
+    if (j >= 1) u1 = make_upd(64, mr, p + NB, ge, p - NB, NB);
     // G = 1: the previous panel on all later columns; grouped: the previous
     // group on the rest of this group's columns, beside its first panel
-    if (g >= 1 && (G == 1 || j == 0)) u2 = make_upd(sbm, mr, p + NB, G == 1 ? mc : ge, gs - GW, GW);
+    if (g >= 1 && (G == 1 || j == 0)) u2 = make_upd(64, mr, p + NB, G == 1 ? mc : ge, gs - GW, GW);
     const int ntiles = u1.ntiles + u2.ntiles;
     const int per_xcd = cdiv(ntiles, 8);
     const int npw = ntiles ? cdiv(npw_need, 8) * 8 : npw_need;
-    if (sbm == 128)
-      hipLaunchKernelGGL(k_chol_step<128>, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M,
-                         ld, p, diag, info, npw_need, npw, u1, u2, per_xcd);
-    else
-      hipLaunchKernelGGL(k_chol_step<64>, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M,
-                         ld, p, diag, info, npw_need, npw, u1, u2, per_xcd);
+    hipLaunchKernelGGL(k_chol_step<64>, dim3(npw + 8 * per_xcd), dim3(256), 0, st, mr, mc, M, ld,
+                       p, diag, info, npw_need, npw, u1, u2, per_xcd);
     const int q = p + NB;
     if (q >= mc) continue;
     if (!big || q < ge) {
@@ -1043,9 +1046,9 @@ void launch_potrf_f64(hipStream_t st, int mr, int mc, double* M, long ld, DevInf
                 hipStreamWaitEvent(sb, aux->ev_main, 0) != hipSuccess))
       drop_aux();
     if (ne < mc) {
-      const CholUpd uo = make_upd(bm, mr, ne, mc, gs, GW);
+      const CholUpd uo = make_upd(128, mr, ne, mc, gs, GW);
       const int gx = uo.ntiles < kUpdGroups ? uo.ntiles : kUpdGroups;
-      hipLaunchKernelGGL(k_chol_upd<128>, dim3(gx), dim3(256), 0, sb, mr, M, ld, uo);
+      hipLaunchKernelGGL(k_chol_upd<128>, dim3(gx), dim3(512), 0, sb, mr, M, ld, uo);
     }
     if (two && aux_pending && hipStreamWaitEvent(st, aux->ev_aux, 0) != hipSuccess) drop_aux();
     if (two) {
