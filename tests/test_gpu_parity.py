@@ -55,12 +55,13 @@ def test_normal_matrix(torch_dev, m, n):
     assert np.all(Mg[~low] == 0.0)  # upper triangle untouched
 
 
-@pytest.mark.parametrize("m", [1, 64, 100, 200, 333, 700, 4133])
+@pytest.mark.parametrize("m", [1, 64, 100, 200, 333, 700, 4096, 4133])
 def test_cholesky_and_solve(torch_dev, m):
-    """Factor and solve against the oracle; m = 4133 takes the grouped
-    schedule of large matrices (panels by four, each group's update of the
-    columns beyond the next group on a second stream), ending in a ragged
-    group, and is factored twice to the same bits."""
+    """Factor and solve against the oracle; m = 4096 (the threshold, whole
+    groups) and 4133 (ending in a ragged group) take the grouped schedule of
+    large matrices (panels by four, each group's update of the columns
+    beyond the next group on a second stream) and are factored twice to the
+    same bits."""
     torch, dev = torch_dev
     from paper_1502_03543_amd import solver
     rng = np.random.default_rng(m)
